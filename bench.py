@@ -1,0 +1,210 @@
+"""Throughput of the spin-1 split-step hot path on one MI355X.
+
+Workload: 2D 512 x 512 periodic grid, 64 truncated-Wigner samples, complex64
+bulk with FP64 reductions, c0 = 1, c1 = -0.1, q = 0.09 (quench into the
+easy-plane phase), dt = 0.02.  One bench step = 100 split steps of every
+sample plus one structure-factor snapshot (the snapshot cadence of the
+workload), so the default 100 steps are the full 10^4-step run.  The initial
+Wigner state is drawn once before the timed region.
+
+Prints one JSON line: site-steps/s (whole job), the roofline entry of the
+dominant kernel (algorithmic bytes / live HIP-event time), the complex128
+rate and speedup, the FP32-vs-FP64 error after 100 steps, and the oracle's
+rate on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+WORKLOAD = dict(dim=2, n=(512, 512), dx=0.5, samples=64, dt=0.02, split_steps=100,
+                params=dict(c0=1.0, c1=-0.1, q=0.09, n0=1.0, wigner_var=0.5), seed=1002)
+
+
+def algorithmic_bytes(kind, grid, cbytes):
+    """Bytes one launch of a pass kind must move: the 3-component field read
+    and written once (48 B per site in complex64, 96 B in complex128)."""
+    dim, n, samples = grid
+    sites = 1
+    for v in n:
+        sites *= v
+    if kind in ("xpass", "ypass", "zpass", "local"):
+        return 2 * 3 * cbytes * sites * samples
+    return None
+
+
+def run_gpu(dtype, steps, warmup, profile):
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    w = WORKLOAD
+    grid = (w["dim"], w["n"], w["dx"], w["samples"])
+    sim = spin1.Sim([grid], w["params"], dtype=dtype)
+    sim.init_wigner(w["seed"])
+    torch.cuda.synchronize()
+
+    def bench_step():
+        sim.step(w["split_steps"], w["dt"])
+        sim.structure_factor_samples()
+
+    for _ in range(warmup):
+        bench_step()
+    torch.cuda.synchronize()
+    if profile:
+        spin1.profile_read(sim.ctx)  # clear
+        spin1.profile_enable(sim.ctx, True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        bench_step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = spin1.profile_read(sim.ctx) if profile else None
+    if profile:
+        spin1.profile_enable(sim.ctx, False)
+    ev_ms = start.elapsed_time(stop)
+    return sim, wall, ev_ms, prof
+
+
+def fp32_vs_fp64_error():
+    """Relative L2 distance of the complex64 and complex128 fields after 100
+    split steps from the same Wigner state (whole workload)."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    w = WORKLOAD
+    grid = (w["dim"], w["n"], w["dx"], w["samples"])
+    out = []
+    for dt in ("c64", "c128"):
+        sim = spin1.Sim([grid], w["params"], dtype=dt)
+        sim.init_wigner(w["seed"])
+        sim.step(w["split_steps"], w["dt"])
+        torch.cuda.synchronize()
+        out.append(sim.psi[0].to(torch.complex128))
+        sim.close()
+    err = (torch.linalg.vector_norm(out[0] - out[1]) / torch.linalg.vector_norm(out[1])).item()
+    del out
+    torch.cuda.empty_cache()
+    return err
+
+
+def oracle_baseline(budget_s=20.0):
+    """The FP64 oracle on the host: one sample of the 512 x 512 workload,
+    split steps until about budget_s seconds have passed."""
+    import numpy as np
+    from oracle import spin1 as O
+
+    w = WORKLOAD
+    g = O.Grid(2, w["n"], w["dx"], 1)
+    p = O.Params(**w["params"])
+    psi = O.init_wigner(w["seed"], g, p)
+    t0 = time.perf_counter()
+    nsteps = 0
+    while True:
+        psi = O.strang_step(psi, w["dt"], p, g)
+        nsteps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    assert np.isfinite(psi).all()
+    return g.sites * nsteps / el, nsteps, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the Wigner samples are independent, so N GPUs would each run "
+              "this same single-GPU workload on their own share (see DESIGN.md); --gpus %d is not run."
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_03636_amd import spin1
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    spin1.load()
+
+    w = WORKLOAD
+    sites = w["n"][0] * w["n"][1]
+    per_step_site_steps = w["samples"] * sites * w["split_steps"]
+    grid = (w["dim"], w["n"], w["samples"])
+
+    sim, wall, ev_ms, prof = run_gpu("c64", args.steps, args.warmup, profile=True)
+    value = per_step_site_steps * args.steps / (ev_ms / 1e3)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    # dominant kernel and its live average duration
+    kinds = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    dom_ms, dom_n = kinds[dom]
+    dom_avg_ms = dom_ms / dom_n
+    dom_bytes = algorithmic_bytes(dom, grid, 8)
+    achieved = dom_bytes / (dom_avg_ms / 1e3) / 1e9 if dom_bytes else None
+
+    sim64, wall64, ev64, _ = run_gpu("c128", args.fp64_steps, 1, profile=False)
+    value64 = per_step_site_steps * args.fp64_steps / (ev64 / 1e3)
+    sim64.close()
+    del sim64
+    torch.cuda.empty_cache()
+
+    err = fp32_vs_fp64_error()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rate, n_cpu, el = oracle_baseline(args.cpu_budget)
+        cpu = {"value": rate, "unit": "site-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "FP64 numpy oracle, 1 sample of the 512x512 grid, %d Strang steps in %.1f s "
+                         "(numpy elementwise ops and batched 3x3 eigh run on one thread)" % (n_cpu, el)}
+
+    line = {
+        "metric": "site-steps/s, spin-1 split-step (FP32 vs FP64 at stated err); HBM GB/s",
+        "value": value,
+        "unit": "site-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ev_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded truncated-Wigner polar state (Philox4x64-10), no dataset",
+        "config": {"workload": "2D 512x512 periodic spin-1 GPE, 64 Wigner samples, complex64 bulk + FP64 "
+                               "reductions, dt=0.02; step = 100 split steps + 1 structure-factor snapshot",
+                   "grid": list(w["n"]), "samples": w["samples"], "split_steps_per_step": w["split_steps"],
+                   "dt": w["dt"], "params": w["params"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
+                     "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes},
+        "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
+        "hbm_algorithmic_GBps_whole_step": None,
+        "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
+                 "ms_per_step": ev64 / args.fp64_steps},
+        "speedup_fp32_vs_fp64": value / value64,
+        "err_fp32_vs_fp64_rel_l2_100_split_steps": err,
+        "wall_s": wall,
+        "cpu_baseline": cpu,
+    }
+    # whole-step algorithmic bandwidth: 2 passes x 48 B per site per split step
+    line["hbm_algorithmic_GBps_whole_step"] = value * 2 * 48 / 1e9
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * spin1.h -- C ABI of the MI355X spin-1 split-step library.
+ *
+ * The library propagates many truncated-Wigner samples of the three-component
+ * (spin-1) Gross-Pitaevskii equation, Eq. (2) of arXiv:2310.03636
+ * ("Universal Dynamics at the Lowest Temperatures", Sec. 2.2), with a
+ * split-step Fourier method (Sec. 2.2, Eqs. (3)-(5)), and evaluates the
+ * sample-averaged structure factor S(t,k) = <F_perp(t,k)^* F_perp(t,k)> of the
+ * transverse spin F_perp = F_x + i F_y (Sec. 2.1, the paragraph before
+ * Eq. (1)).
+ *
+ * Units hbar = m = 1.  Components are ordered (psi_{+1}, psi_0, psi_{-1}) as
+ * in Eq. (2).  A field of one group is a device array [S][3][Nz][Ny][Nx] of
+ * interleaved complex numbers (x fastest): complex64 (2 x float) or
+ * complex128 (2 x double).
+ *
+ * Memory ownership: the caller owns every device buffer (fields, workspace,
+ * outputs) and passes raw device pointers; the library only borrows them
+ * between spin1_bind / spin1_init_wigner and spin1_destroy or the next bind.
+ * The library allocates no device memory of its own.
+ *
+ * Streams: all device work is enqueued on the HIP stream given to
+ * spin1_create and is asynchronous; results in device buffers are valid
+ * once that stream has completed the call.  A context is not thread-safe.
+ *
+ * Errors: every int-returning function returns SPIN1_OK (0) or a negative
+ * status; spin1_last_error() returns a thread-local message for the last
+ * failure.  Arguments are validated before anything is launched; a call that
+ * fails validation changes no state.  Faults of kernels that already run
+ * surface as SPIN1_EHIP at a later call that checks the stream.
+ */
+#ifndef SPIN1_H
+#define SPIN1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define SPIN1_API __attribute__((visibility("default")))
+#else
+#define SPIN1_API
+#endif
+
+typedef struct spin1_ctx spin1_ctx;
+
+enum spin1_status {
+  SPIN1_OK = 0,
+  SPIN1_EINVAL = -1,       /* invalid argument */
+  SPIN1_EUNSUPPORTED = -2, /* valid but not supported by the compiled kernels */
+  SPIN1_EHIP = -3,         /* HIP runtime error */
+  SPIN1_ESTATE = -4,       /* call out of order (e.g. step before bind) */
+  SPIN1_ENOMEM = -5        /* a host allocation failed */
+};
+
+enum spin1_dtype { SPIN1_C64 = 0, SPIN1_C128 = 1 };
+
+/* A periodic lattice with `samples` independent runs.  dim in {1,2,3};
+ * n[a] points along axis a (x, y, z), n[a] = 1 for a >= dim; dx > 0 the
+ * lattice spacing (lengths in the units of Eq. (2) with hbar = m = 1).
+ * Supported sizes: every n[a] (a < dim) a power of two; 8 <= Nx <= 4096 in
+ * 1D; 16 <= Nx <= 4096 and 8 <= Ny, Nz <= 1024 in 2D and 3D. */
+typedef struct {
+  int32_t dim;
+  int32_t n[3];
+  double dx;
+  int32_t samples;
+} spin1_grid;
+
+/* Couplings of Eq. (2): c0 (density), c1 (spin), q (quadratic Zeeman, acts
+ * on m = +1 and m = -1 only); n0 the condensate density of the polar initial
+ * state psi_0 = sqrt(n0); wigner_var the Wigner noise per plane-wave mode
+ * (per-site variance wigner_var / dx^dim per component; 1/2 = half a
+ * quantum). */
+typedef struct {
+  double c0, c1, q, n0, wigner_var;
+} spin1_params;
+
+/* Create a context for fields of the given dtype on the current HIP device.
+ * stream: a hipStream_t (may be NULL for the default stream).  *out is set on
+ * success; free it with spin1_destroy. */
+SPIN1_API int spin1_create(spin1_ctx** out, int32_t dtype, void* stream);
+SPIN1_API int spin1_destroy(spin1_ctx* ctx);
+
+/* Host-only helpers (no device work).  Invalid grids give 0 / a negative
+ * status and set the error message. */
+SPIN1_API int spin1_check_grid(const spin1_grid* g, int32_t dtype);
+SPIN1_API size_t spin1_field_bytes(const spin1_grid* g, int32_t dtype);  /* S*3*sites*sizeof(complex) */
+SPIN1_API size_t spin1_workspace_bytes(const spin1_grid* groups, int32_t n_groups, int32_t dtype);
+/* Radial shells of the structure factor: shell b collects the modes whose
+ * integer index vector j' (signed DFT index per axis, scaled to the finest
+ * axis spacing) has |j'| nearest to b.  Returns the number of shells or a
+ * negative status. */
+SPIN1_API int32_t spin1_num_bins(const spin1_grid* g);
+/* counts_host[b] = number of modes in shell b (array of spin1_num_bins). */
+SPIN1_API int spin1_bin_counts(const spin1_grid* g, int64_t* counts_host);
+
+/* Bind n_groups fields (psi_dev[g]: device array of spin1_field_bytes) and a
+ * workspace of spin1_workspace_bytes bytes to the context, with the couplings
+ * p.  Host index tables for the shells are uploaded synchronously. */
+SPIN1_API int spin1_bind(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const spin1_params* p,
+               void* const* psi_dev, void* workspace_dev);
+
+/* spin1_bind, then fill every bound field with the truncated-Wigner initial
+ * state of Sec. 2.2 (runs from weakly fluctuating initial conditions): a polar
+ * condensate psi_0 = sqrt(n0) plus complex Gaussian noise of variance
+ * wigner_var / dx^dim on every component.  The noise of (site, component,
+ * sample, group) comes from one Philox4x64-10 block with that counter and key
+ * (seed, 0) (Box-Muller of its first two words), so every sample is
+ * reproducible on its own. */
+SPIN1_API int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
+                      const spin1_params* p, void* const* psi_dev, void* workspace_dev);
+
+/* Replace the couplings between steps (a quench of q, Sec. 2.1, Fig. 1). */
+SPIN1_API int spin1_set_params(spin1_ctx* ctx, const spin1_params* p);
+
+/* Advance every bound group by n steps of dt (dt may be negative): each step
+ * is the symmetric split R(dt/2) [K Q](dt) R(dt/2) of the operator of Eq. (2),
+ * R the exact local (c0, c1) update (the interaction sub-steps, Eqs. (4)-(5)),
+ * K the kinetic phase of Eq. (3) and Q the quadratic Zeeman phase.  Adjacent
+ * half steps are merged inside the call; the field is at t + n dt on return. */
+SPIN1_API int spin1_step(spin1_ctx* ctx, int64_t n, double dt);
+
+/* Per-sample shell means of |DFT F_perp(k)|^2 / N_sites for group `group`
+ * (the sample average of these is S(t,k) of Sec. 2.1; a shell without modes
+ * reports 0): bins_dev is a device array [S][spin1_num_bins] of double. */
+SPIN1_API int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins_dev);
+
+/* Per-sample (N, F_z, E) in FP64 for group `group`: obs_dev is a device array
+ * [S][3] of double, N = dx^d sum n, F_z = dx^d sum (|psi_1|^2 - |psi_-1|^2),
+ * E the energy whose Wirtinger derivative is the right-hand side of Eq. (2). */
+SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
+
+/* Apply the exact local update R(tau) alone to every bound field (Eqs. (4)-(5)
+ * combined, q excluded). */
+SPIN1_API int spin1_local_update(spin1_ctx* ctx, double tau);
+
+/* Kernel kinds reported by the profiling hooks. */
+enum spin1_kernel_kind {
+  SPIN1_K_XPASS = 0,       /* x-pass of a step (local update, FFT_x, phase, IFFT_x) */
+  SPIN1_K_YPASS = 1,       /* y-pass of a step */
+  SPIN1_K_ZPASS = 2,       /* z-pass of a step */
+  SPIN1_K_LOCAL = 3,       /* stand-alone local update (closing half step) */
+  SPIN1_K_SPECTRUM = 4,    /* F_perp transforms of the structure factor */
+  SPIN1_K_SHELLS = 5,      /* radial shell sums */
+  SPIN1_K_OBSERVABLES = 6, /* energy / norm / F_z passes */
+  SPIN1_K_OTHER = 7,       /* tables and initial state */
+  SPIN1_K_COUNT = 8
+};
+
+/* Profiling: when enabled, every kernel launch is bracketed by two HIP events
+ * on the context's stream.  spin1_profile_read synchronises the stream, adds
+ * the elapsed times per kind into ms[kind] and the launch counts into
+ * launches[kind] (arrays of n_kinds <= SPIN1_K_COUNT entries, overwritten),
+ * and clears the record.  Events are created on first use and reused. */
+SPIN1_API int spin1_profile_enable(spin1_ctx* ctx, int32_t enable);
+SPIN1_API int spin1_profile_read(spin1_ctx* ctx, double* ms, int64_t* launches, int32_t n_kinds);
+
+/* Message of the last failure on this thread; never NULL. */
+SPIN1_API const char* spin1_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPIN1_H */

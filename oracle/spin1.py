@@ -381,9 +381,11 @@ def structure_factor(psi, grid):
     b = bin_index(grid).ravel()
     nb = int(b.max()) + 1
     counts = np.bincount(b, minlength=nb).astype(np.float64)
-    out = np.empty((grid.samples, nb))
+    out = np.zeros((grid.samples, nb))
+    filled = counts > 0  # a shell without modes reports 0
     for s in range(grid.samples):
-        out[s] = np.bincount(b, weights=power[s].ravel(), minlength=nb) / counts
+        sums = np.bincount(b, weights=power[s].ravel(), minlength=nb)
+        out[s, filled] = sums[filled] / counts[filled]
     return out
 
 

@@ -1,0 +1,606 @@
+// C ABI of the spin-1 split-step library: validation, workspace layout,
+// shell index tables, and the host-side order of the passes.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spin1.h"
+#include "internal.hpp"
+
+using namespace spin1;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SPIN1_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+int validate_grid(const spin1_grid* g, int32_t dtype) {
+  if (!g) return fail(SPIN1_EINVAL, "grid pointer is NULL");
+  if (dtype != SPIN1_C64 && dtype != SPIN1_C128) return fail(SPIN1_EINVAL, "dtype %d is not SPIN1_C64/SPIN1_C128", dtype);
+  if (g->dim < 1 || g->dim > 3) return fail(SPIN1_EINVAL, "dim must be 1, 2 or 3 (got %d)", g->dim);
+  if (!(g->dx > 0.0) || !isfinite(g->dx)) return fail(SPIN1_EINVAL, "dx must be finite and > 0");
+  if (g->samples < 1) return fail(SPIN1_EINVAL, "samples must be >= 1 (got %d)", g->samples);
+  for (int a = 0; a < 3; ++a) {
+    const int n = g->n[a];
+    if (a >= g->dim) {
+      if (n != 1) return fail(SPIN1_EINVAL, "n[%d] must be 1 for a %d-dimensional grid (got %d)", a, g->dim, n);
+      continue;
+    }
+    if (!is_pow2(n)) return fail(SPIN1_EINVAL, "n[%d] = %d is not a power of two", a, n);
+    if (n < 8) return fail(SPIN1_EINVAL, "n[%d] = %d is below the minimum 8", a, n);
+    if (a == 0) {
+      if (n > 4096) return fail(SPIN1_EUNSUPPORTED, "Nx = %d exceeds 4096", n);
+      if (g->dim > 1 && n < 16) return fail(SPIN1_EUNSUPPORTED, "Nx = %d: 2D/3D grids need Nx >= 16", n);
+    } else if (n > 1024) {
+      return fail(SPIN1_EUNSUPPORTED, "n[%d] = %d: strided axes support at most 1024 points", a, n);
+    }
+  }
+  const int64_t sites = int64_t(g->n[0]) * g->n[1] * g->n[2];
+  if (sites * g->samples * 3 > (int64_t(1) << 40)) return fail(SPIN1_EUNSUPPORTED, "field too large");
+  return SPIN1_OK;
+}
+
+Geom geom_of(const spin1_grid* g) {
+  Geom r;
+  r.dim = g->dim;
+  for (int a = 0; a < 3; ++a) r.n[a] = g->n[a];
+  r.dx = g->dx;
+  r.S = g->samples;
+  r.sites = int64_t(g->n[0]) * g->n[1] * g->n[2];
+  r.rows = r.sites / g->n[0];
+  return r;
+}
+
+double cell_of(const Geom& g) {
+  double c = 1.0;
+  for (int a = 0; a < g.dim; ++a) c *= g.dx;
+  return c;
+}
+
+int64_t isqrt64(int64_t v) {
+  int64_t s = int64_t(sqrt(double(v)));
+  while (s > 0 && s * s > v) --s;
+  while ((s + 1) * (s + 1) <= v) ++s;
+  return s;
+}
+
+// shell of integer |j'|^2 = J: the b with 4J < (2b+1)^2 and (2b-1)^2 <= 4J for b >= 1
+int shell_of(int64_t J) { return int((isqrt64(4 * J) + 1) / 2); }
+
+int nmax_of(const Geom& g) {
+  int m = 1;
+  for (int a = 0; a < g.dim; ++a) m = std::max(m, g.n[a]);
+  return m;
+}
+
+int64_t mode_J(const Geom& g, int64_t site) {
+  const int nm = nmax_of(g);
+  int64_t J = 0;
+  int64_t rest = site;
+  for (int a = 0; a < g.dim; ++a) {
+    const int n = g.n[a];
+    const int64_t j = rest % n;
+    rest /= n;
+    const int64_t js = (j < n / 2 ? j : j - n) * (nm / n);
+    J += js * js;
+  }
+  return J;
+}
+
+int num_bins_of(const Geom& g) {
+  const int64_t h = nmax_of(g) / 2;
+  return shell_of(int64_t(g.dim) * h * h) + 1;
+}
+
+struct Layout {
+  size_t ph[3] = {0, 0, 0}, tw[3] = {0, 0, 0}, part[3] = {0, 0, 0};
+  int64_t nblk[3] = {0, 0, 0};  // partial entries (y, z: one per workgroup)
+  size_t sff = 0, pow = 0, perm = 0, offs = 0, end = 0;
+};
+
+// spass geometry for axis a (1 = y, 2 = z)
+void spass_geom(const Geom& g, int a, int64_t* sa, int64_t* inner, int64_t* outer, int64_t* outer_stride) {
+  const int64_t nx = g.n[0], ny = g.n[1];
+  if (a == 1) {
+    *sa = nx;
+    *inner = nx;
+    *outer = g.dim == 3 ? g.n[2] : 1;
+    *outer_stride = nx * ny;
+  } else {
+    *sa = nx * ny;
+    *inner = nx * ny;
+    *outer = 1;
+    *outer_stride = 0;
+  }
+}
+
+size_t layout_group(const Geom& g, bool dbl, size_t base, Layout* L) {
+  const size_t cb = dbl ? 16 : 8, rb = dbl ? 8 : 4;
+  size_t off = base;
+  for (int a = 0; a < g.dim; ++a) {
+    L->ph[a] = off;
+    off = align_up(off + size_t(a == 0 ? 3 : 1) * g.n[a] * cb);
+    L->tw[a] = off;
+    off = align_up(off + size_t(g.n[a]) * cb);
+  }
+  L->part[0] = off;
+  off = align_up(off + size_t(g.S) * g.rows * 4 * sizeof(double));
+  for (int a = 1; a < g.dim; ++a) {
+    int64_t sa, inner, outer, os;
+    spass_geom(g, a, &sa, &inner, &outer, &os);
+    const int tx = spass_tx(g.n[a], dbl);
+    L->nblk[a] = int64_t(3) * g.S * outer * (inner / tx);
+    L->part[a] = off;
+    off = align_up(off + size_t(L->nblk[a]) * sizeof(double));
+  }
+  if (g.dim > 1) {
+    L->sff = off;
+    off = align_up(off + size_t(g.S) * g.sites * cb);
+  }
+  L->pow = off;
+  off = align_up(off + size_t(g.S) * g.sites * rb);
+  L->perm = off;
+  off = align_up(off + size_t(g.sites) * sizeof(int32_t));
+  L->offs = off;
+  off = align_up(off + size_t(num_bins_of(g) + 1) * sizeof(int32_t));
+  L->end = off;
+  return off;
+}
+
+struct GroupState {
+  spin1_grid grid;
+  Geom geo;
+  void* psi;
+  Layout lay;
+  int nbins;
+};
+
+}  // namespace
+
+struct ProfRecord {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+struct spin1_ctx {
+  int dtype = SPIN1_C64;
+  bool dbl = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool bound = false;
+  spin1_params p{};
+  std::vector<GroupState> groups;
+  char* ws = nullptr;
+  bool tab_valid = false;
+  double tab_dt = 0.0, tab_q = 0.0;
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;  // created events, reused
+  std::vector<ProfRecord> rec;      // records since the last read
+  size_t ev_used = 0;
+  ~spin1_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int check_ctx(spin1_ctx* ctx, bool need_bound) {
+  if (!ctx) return fail(SPIN1_EINVAL, "context is NULL");
+  if (need_bound && !ctx->bound) return fail(SPIN1_ESTATE, "no field bound: call spin1_bind or spin1_init_wigner first");
+  return SPIN1_OK;
+}
+
+int validate_params(const spin1_params* p) {
+  if (!p) return fail(SPIN1_EINVAL, "params pointer is NULL");
+  const double v[5] = {p->c0, p->c1, p->q, p->n0, p->wigner_var};
+  for (double x : v)
+    if (!isfinite(x)) return fail(SPIN1_EINVAL, "params must be finite");
+  if (p->n0 < 0.0) return fail(SPIN1_EINVAL, "n0 must be >= 0");
+  if (p->wigner_var < 0.0) return fail(SPIN1_EINVAL, "wigner_var must be >= 0");
+  return SPIN1_OK;
+}
+
+char* at(spin1_ctx* ctx, size_t off) { return ctx->ws + off; }
+
+hipEvent_t next_event(spin1_ctx* ctx) {
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  return ctx->ev_pool[ctx->ev_used++];
+}
+
+// Brackets one launch with events when profiling is on.
+struct Prof {
+  spin1_ctx* ctx;
+  int kind;
+  hipEvent_t a = nullptr;
+  Prof(spin1_ctx* c, int k) : ctx(c), kind(k) {
+    if (ctx->prof && (a = next_event(ctx))) (void)hipEventRecord(a, ctx->stream);
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = next_event(ctx);
+    if (!b) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->rec.push_back(ProfRecord{kind, a, b});
+  }
+};
+
+int make_tables(spin1_ctx* ctx, double dt) {
+  for (auto& G : ctx->groups) {
+    for (int a = 0; a < G.geo.dim; ++a) {
+      Prof pr(ctx, SPIN1_K_OTHER);
+      const hipError_t e = launch_tables(ctx->stream, ctx->dbl, at(ctx, G.lay.ph[a]), at(ctx, G.lay.tw[a]), G.geo.n[a],
+                                         a == 0 ? 3 : 1, dt, ctx->p.q, G.geo.dx);
+      if (e != hipSuccess) return hip_fail(e, "table kernel");
+    }
+  }
+  ctx->tab_valid = true;
+  ctx->tab_dt = dt;
+  ctx->tab_q = ctx->p.q;
+  return SPIN1_OK;
+}
+
+int upload_shells(spin1_ctx* ctx, GroupState& G) {
+  const Geom& g = G.geo;
+  const int nb = G.nbins;
+  std::vector<int32_t> offs(size_t(nb) + 1, 0), perm;
+  std::vector<int32_t> shell;
+  try {
+    perm.resize(size_t(g.sites));
+    shell.resize(size_t(g.sites));
+  } catch (const std::bad_alloc&) {
+    return fail(SPIN1_ENOMEM, "host allocation of shell tables failed");
+  }
+  for (int64_t s = 0; s < g.sites; ++s) {
+    const int b = shell_of(mode_J(g, s));
+    shell[size_t(s)] = b;
+    offs[size_t(b) + 1]++;
+  }
+  for (int b = 0; b < nb; ++b) offs[size_t(b) + 1] += offs[size_t(b)];
+  std::vector<int32_t> fill(offs.begin(), offs.end() - 1);
+  for (int64_t s = 0; s < g.sites; ++s) perm[size_t(fill[size_t(shell[size_t(s)])]++)] = int32_t(s);
+  hipError_t e = hipMemcpy(at(ctx, G.lay.perm), perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload of shell permutation");
+  e = hipMemcpy(at(ctx, G.lay.offs), offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload of shell offsets");
+  return SPIN1_OK;
+}
+
+XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
+  XPassArgs a{};
+  a.psi = G.psi;
+  a.tw = at(ctx, G.lay.tw[0]);
+  a.ph = at(ctx, G.lay.ph[0]);
+  a.rows = G.geo.rows;
+  a.sites = G.geo.sites;
+  a.S = G.geo.S;
+  a.c0 = ctx->p.c0;
+  a.c1 = ctx->p.c1;
+  a.q = ctx->p.q;
+  a.kscale = 2.0 * M_PI / (double(G.geo.n[0]) * G.geo.dx);
+  a.power_scale = 1.0 / double(G.geo.sites);
+  return a;
+}
+
+SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int64_t nfield) {
+  SPassArgs a{};
+  a.psi = field;
+  a.tw = at(ctx, G.lay.tw[axis]);
+  a.ph = at(ctx, G.lay.ph[axis]);
+  spass_geom(G.geo, axis, &a.sa, &a.inner, &a.outer, &a.outer_stride);
+  a.nfield = nfield;
+  a.field_stride = G.geo.sites;
+  a.kscale = 2.0 * M_PI / (double(G.geo.n[axis]) * G.geo.dx);
+  a.power_scale = 1.0 / double(G.geo.sites);
+  return a;
+}
+
+int bind_impl(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const spin1_params* p,
+              void* const* psi_dev, void* ws) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  if (n_groups < 1 || !groups) return fail(SPIN1_EINVAL, "need at least one group");
+  if (!psi_dev) return fail(SPIN1_EINVAL, "psi_dev is NULL");
+  if (!ws) return fail(SPIN1_EINVAL, "workspace pointer is NULL");
+  if ((rc = validate_params(p))) return rc;
+  for (int i = 0; i < n_groups; ++i) {
+    if ((rc = validate_grid(&groups[i], ctx->dtype))) return rc;
+    if (!psi_dev[i]) return fail(SPIN1_EINVAL, "psi_dev[%d] is NULL", i);
+    if (reinterpret_cast<uintptr_t>(psi_dev[i]) % (ctx->dbl ? 16 : 8))
+      return fail(SPIN1_EINVAL, "psi_dev[%d] is not aligned to the complex size", i);
+  }
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(SPIN1_EINVAL, "workspace must be 256-byte aligned");
+  std::vector<GroupState> gs(static_cast<size_t>(n_groups));
+  size_t off = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    gs[size_t(i)].grid = groups[i];
+    gs[size_t(i)].geo = geom_of(&groups[i]);
+    gs[size_t(i)].psi = psi_dev[i];
+    gs[size_t(i)].nbins = num_bins_of(gs[size_t(i)].geo);
+    off = layout_group(gs[size_t(i)].geo, ctx->dbl, off, &gs[size_t(i)].lay);
+  }
+  ctx->groups.swap(gs);
+  ctx->ws = static_cast<char*>(ws);
+  ctx->p = *p;
+  ctx->bound = true;
+  ctx->tab_valid = false;
+  for (auto& G : ctx->groups)
+    if ((rc = upload_shells(ctx, G))) {
+      ctx->bound = false;
+      return rc;
+    }
+  if ((rc = make_tables(ctx, 0.0))) {
+    ctx->bound = false;
+    return rc;
+  }
+  return SPIN1_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spin1_last_error(void) { return g_err.c_str(); }
+
+int spin1_check_grid(const spin1_grid* g, int32_t dtype) { return validate_grid(g, dtype); }
+
+size_t spin1_field_bytes(const spin1_grid* g, int32_t dtype) {
+  if (validate_grid(g, dtype)) return 0;
+  const Geom G = geom_of(g);
+  return size_t(G.S) * 3 * size_t(G.sites) * (dtype == SPIN1_C128 ? 16 : 8);
+}
+
+size_t spin1_workspace_bytes(const spin1_grid* groups, int32_t n_groups, int32_t dtype) {
+  if (!groups || n_groups < 1) {
+    fail(SPIN1_EINVAL, "need at least one group");
+    return 0;
+  }
+  size_t off = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    if (validate_grid(&groups[i], dtype)) return 0;
+    Layout L;
+    off = layout_group(geom_of(&groups[i]), dtype == SPIN1_C128, off, &L);
+  }
+  return off;
+}
+
+int32_t spin1_num_bins(const spin1_grid* g) {
+  const int rc = validate_grid(g, SPIN1_C64);
+  if (rc) return rc;
+  return num_bins_of(geom_of(g));
+}
+
+int spin1_bin_counts(const spin1_grid* g, int64_t* counts) {
+  int rc = validate_grid(g, SPIN1_C64);
+  if (rc) return rc;
+  if (!counts) return fail(SPIN1_EINVAL, "counts pointer is NULL");
+  const Geom G = geom_of(g);
+  const int nb = num_bins_of(G);
+  for (int b = 0; b < nb; ++b) counts[b] = 0;
+  for (int64_t s = 0; s < G.sites; ++s) counts[shell_of(mode_J(G, s))]++;
+  return SPIN1_OK;
+}
+
+int spin1_create(spin1_ctx** out, int32_t dtype, void* stream) {
+  if (!out) return fail(SPIN1_EINVAL, "out pointer is NULL");
+  if (dtype != SPIN1_C64 && dtype != SPIN1_C128) return fail(SPIN1_EINVAL, "dtype %d is not SPIN1_C64/SPIN1_C128", dtype);
+  int dev = 0;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  spin1_ctx* c = new (std::nothrow) spin1_ctx;
+  if (!c) return fail(SPIN1_ENOMEM, "context allocation failed");
+  c->dtype = dtype;
+  c->dbl = dtype == SPIN1_C128;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->device = dev;
+  *out = c;
+  return SPIN1_OK;
+}
+
+int spin1_destroy(spin1_ctx* ctx) {
+  if (!ctx) return fail(SPIN1_EINVAL, "context is NULL");
+  delete ctx;
+  return SPIN1_OK;
+}
+
+int spin1_bind(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const spin1_params* p,
+               void* const* psi_dev, void* workspace_dev) {
+  return bind_impl(ctx, groups, n_groups, p, psi_dev, workspace_dev);
+}
+
+int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
+                      const spin1_params* p, void* const* psi_dev, void* workspace_dev) {
+  int rc = bind_impl(ctx, groups, n_groups, p, psi_dev, workspace_dev);
+  if (rc) return rc;
+  for (size_t i = 0; i < ctx->groups.size(); ++i) {
+    const GroupState& G = ctx->groups[i];
+    Prof pr(ctx, SPIN1_K_OTHER);
+    const hipError_t e =
+        launch_init(ctx->stream, ctx->dbl, G.psi, G.geo, seed, uint64_t(i), ctx->p.n0, ctx->p.wigner_var);
+    if (e != hipSuccess) return hip_fail(e, "init kernel");
+  }
+  return SPIN1_OK;
+}
+
+int spin1_set_params(spin1_ctx* ctx, const spin1_params* p) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if ((rc = validate_params(p))) return rc;
+  ctx->p = *p;
+  ctx->tab_valid = false;
+  return SPIN1_OK;
+}
+
+int spin1_step(spin1_ctx* ctx, int64_t n, double dt) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (n < 0) return fail(SPIN1_EINVAL, "n must be >= 0");
+  if (!isfinite(dt)) return fail(SPIN1_EINVAL, "dt must be finite");
+  if (n == 0 || dt == 0.0) return SPIN1_OK;
+  if (!ctx->tab_valid || ctx->tab_dt != dt || ctx->tab_q != ctx->p.q)
+    if ((rc = make_tables(ctx, dt))) return rc;
+  for (int64_t i = 0; i < n; ++i) {
+    const double pre = i == 0 ? 0.5 * dt : dt;
+    for (auto& G : ctx->groups) {
+      XPassArgs xa = xargs(ctx, G);
+      xa.tau_pre = pre;
+      xa.tau_post = (G.geo.dim == 1 && i == n - 1) ? 0.5 * dt : 0.0;
+      hipError_t e;
+      {
+        Prof pr(ctx, SPIN1_K_XPASS);
+        e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
+      }
+      if (e != hipSuccess) return hip_fail(e, "x-pass");
+      for (int a = 1; a < G.geo.dim; ++a) {
+        const SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
+        {
+          Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
+          e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
+        }
+        if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
+      }
+      if (G.geo.dim > 1 && i == n - 1) {
+        {
+          Prof pr(ctx, SPIN1_K_LOCAL);
+          e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1);
+        }
+        if (e != hipSuccess) return hip_fail(e, "closing local update");
+      }
+    }
+  }
+  return SPIN1_OK;
+}
+
+int spin1_local_update(spin1_ctx* ctx, double tau) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!isfinite(tau)) return fail(SPIN1_EINVAL, "tau must be finite");
+  for (auto& G : ctx->groups) {
+    Prof pr(ctx, SPIN1_K_LOCAL);
+    const hipError_t e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau, ctx->p.c0, ctx->p.c1);
+    if (e != hipSuccess) return hip_fail(e, "local update");
+  }
+  return SPIN1_OK;
+}
+
+int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!bins_dev) return fail(SPIN1_EINVAL, "bins_dev is NULL");
+  const GroupState& G = ctx->groups[size_t(group)];
+  XPassArgs xa = xargs(ctx, G);
+  hipError_t e;
+  {
+    Prof pr(ctx, SPIN1_K_SPECTRUM);
+    if (G.geo.dim == 1) {
+      xa.out = at(ctx, G.lay.pow);
+      e = launch_xpass(ctx->stream, ctx->dbl, MODE_SF_POWER, G.geo.n[0], xa);
+    } else {
+      xa.out = at(ctx, G.lay.sff);
+      e = launch_xpass(ctx->stream, ctx->dbl, MODE_SF, G.geo.n[0], xa);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "spectrum x-pass");
+  for (int a = 1; a < G.geo.dim; ++a) {
+    SPassArgs sa = sargs(ctx, G, a, at(ctx, G.lay.sff), G.geo.S);
+    const bool last = a == G.geo.dim - 1;
+    sa.out = at(ctx, G.lay.pow);
+    {
+      Prof pr(ctx, SPIN1_K_SPECTRUM);
+      e = launch_spass(ctx->stream, ctx->dbl, last ? MODE_SF_POWER : MODE_SF, G.geo.n[a], sa);
+    }
+    if (e != hipSuccess) return hip_fail(e, "spectrum strided pass");
+  }
+  Prof pr(ctx, SPIN1_K_SHELLS);
+  e = launch_bin(ctx->stream, ctx->dbl, at(ctx, G.lay.pow), G.geo.S, G.geo.sites,
+                 reinterpret_cast<const int32_t*>(at(ctx, G.lay.perm)),
+                 reinterpret_cast<const int32_t*>(at(ctx, G.lay.offs)), G.nbins, bins_dev);
+  if (e != hipSuccess) return hip_fail(e, "shell kernel");
+  return SPIN1_OK;
+}
+
+int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!obs_dev) return fail(SPIN1_EINVAL, "obs_dev is NULL");
+  const GroupState& G = ctx->groups[size_t(group)];
+  XPassArgs xa = xargs(ctx, G);
+  xa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[0]));
+  Prof pr(ctx, SPIN1_K_OBSERVABLES);
+  hipError_t e = launch_xpass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[0], xa);
+  if (e != hipSuccess) return hip_fail(e, "energy x-pass");
+  for (int a = 1; a < G.geo.dim; ++a) {
+    SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
+    sa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[a]));
+    e = launch_spass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[a], sa);
+    if (e != hipSuccess) return hip_fail(e, "energy strided pass");
+  }
+  const double* py = G.geo.dim > 1 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[1])) : nullptr;
+  const double* pz = G.geo.dim > 2 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[2])) : nullptr;
+  e = launch_obs_finish(ctx->stream, G.geo.S, reinterpret_cast<const double*>(at(ctx, G.lay.part[0])), G.geo.rows, py,
+                        G.lay.nblk[1] / G.geo.S, pz, G.lay.nblk[2] / G.geo.S, cell_of(G.geo), obs_dev);
+  if (e != hipSuccess) return hip_fail(e, "observables finish");
+  return SPIN1_OK;
+}
+
+int spin1_profile_enable(spin1_ctx* ctx, int32_t enable) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  ctx->prof = enable != 0;
+  return SPIN1_OK;
+}
+
+int spin1_profile_read(spin1_ctx* ctx, double* ms, int64_t* launches, int32_t n_kinds) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  if (!ms || !launches || n_kinds < 1 || n_kinds > SPIN1_K_COUNT)
+    return fail(SPIN1_EINVAL, "need output arrays of 1..%d entries", int(SPIN1_K_COUNT));
+  for (int k = 0; k < n_kinds; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  for (const ProfRecord& r : ctx->rec) {
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, r.start, r.stop);
+    if (e != hipSuccess) return hip_fail(e, "event elapsed time");
+    if (r.kind < n_kinds) {
+      ms[r.kind] += double(t);
+      launches[r.kind] += 1;
+    }
+  }
+  ctx->rec.clear();
+  ctx->ev_used = 0;
+  return SPIN1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,281 @@
+// Device building blocks of the spin-1 split-step library (gfx950).
+//
+//  * Cx<Real>        interleaved complex value (complex64 / complex128 layout)
+//  * dft<Real, R>    in-register radix-R DFT, R = 1, 2, 4, 8, 16
+//  * fft_pencil      Stockham autosort FFT of one pencil of length N, held as
+//                    R values per thread (thread t owns indices t + e*N/R),
+//                    exchanging through LDS between stages
+//  * local_update    exact local (c0, c1) flow over tau at one site
+//  * philox4x64_10   counter-based generator for the Wigner noise
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spin1 {
+
+template <typename Real>
+struct alignas(2 * sizeof(Real)) Cx {
+  Real re, im;
+};
+
+template <typename Real>
+__device__ __forceinline__ Cx<Real> operator+(Cx<Real> a, Cx<Real> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename Real>
+__device__ __forceinline__ Cx<Real> operator-(Cx<Real> a, Cx<Real> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename Real>
+__device__ __forceinline__ Cx<Real> operator*(Cx<Real> a, Cx<Real> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename Real>
+__device__ __forceinline__ Cx<Real> scale(Cx<Real> a, Real s) { return {a.re * s, a.im * s}; }
+template <typename Real>
+__device__ __forceinline__ Cx<Real> conj(Cx<Real> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename Real>
+__device__ __forceinline__ Cx<Real> cmulc(Cx<Real> a, Cx<Real> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename Real>
+__device__ __forceinline__ Real norm2(Cx<Real> a) { return a.re * a.re + a.im * a.im; }
+
+// ---------------------------------------------------------------------------
+// In-register DFT: out[k] = sum_r v[r] exp(-2 pi i r k / R), radix-2 split
+// into even and odd halves, constant twiddles specialised at compile time.
+// ---------------------------------------------------------------------------
+// cos and sin of pi*k/8, k = 0..7
+__device__ constexpr double kCos16[8] = {1.0,
+                                         0.92387953251128675613,
+                                         0.70710678118654752440,
+                                         0.38268343236508977173,
+                                         0.0,
+                                         -0.38268343236508977173,
+                                         -0.70710678118654752440,
+                                         -0.92387953251128675613};
+__device__ constexpr double kSin16[8] = {0.0,
+                                         0.38268343236508977173,
+                                         0.70710678118654752440,
+                                         0.92387953251128675613,
+                                         1.0,
+                                         0.92387953251128675613,
+                                         0.70710678118654752440,
+                                         0.38268343236508977173};
+
+// v * exp(-2 pi i K / R)
+template <typename Real, int R, int K>
+__device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v) {
+  constexpr int I = K * (16 / R);
+  constexpr Real h = Real(0.70710678118654752440);
+  if constexpr (I == 0) {
+    return v;
+  } else if constexpr (I == 4) {
+    return {v.im, -v.re};
+  } else if constexpr (I == 2) {
+    return {h * (v.re + v.im), h * (v.im - v.re)};
+  } else if constexpr (I == 6) {
+    return {h * (v.im - v.re), -h * (v.re + v.im)};
+  } else {
+    constexpr Real c = Real(kCos16[I]);
+    constexpr Real s = Real(kSin16[I]);
+    return {v.re * c + v.im * s, v.im * c - v.re * s};
+  }
+}
+
+template <typename Real, int R, int K>
+__device__ __forceinline__ void dft_combine(Cx<Real>* v, const Cx<Real>* e, const Cx<Real>* o) {
+  if constexpr (K < R / 2) {
+    const Cx<Real> t = twiddle_const<Real, R, K>(o[K]);
+    v[K] = e[K] + t;
+    v[K + R / 2] = e[K] - t;
+    dft_combine<Real, R, K + 1>(v, e, o);
+  }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void dft(Cx<Real>* v) {
+  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  if constexpr (R == 2) {
+    const Cx<Real> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R > 2) {
+    Cx<Real> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    dft<Real, R / 2>(e);
+    dft<Real, R / 2>(o);
+    dft_combine<Real, R, 0>(v, e, o);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stockham FFT of one pencil.  Stage s has radix Rs (R, except a smaller last
+// radix when N is not a power of R) and sub-transform size Ns = product of the
+// earlier radices.  Butterfly b reads indices b + r*N/Rs, multiplies element r
+// by w^(j r) with j = b mod Ns and w = exp(-2 pi i / (Ns Rs)), applies the
+// radix-Rs DFT and writes to (b / Ns) * Ns * Rs + j + r * Ns.  Thread t runs
+// the R/Rs butterflies b = t + u*N/R; the elements it reads are always its own
+// indices t + e*N/R, and in the last stage the outputs land on those same
+// indices, so input and output stay in registers in natural order.
+//
+// Lds: store(i, v), load(i) on the pencil's row and sync() (a workgroup
+// barrier).  tw: table exp(-2 pi i m / N), m < N, in global memory.
+// ---------------------------------------------------------------------------
+template <int N, int R, int Ns>
+struct StageRadix {
+  static constexpr int value = ((N / Ns) % R == 0) ? R : (N / Ns);
+};
+
+template <typename Real, int N, int R, int Ns, class Lds>
+__device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw) {
+  if constexpr (Ns < N) {
+    constexpr int Rs = StageRadix<N, R, Ns>::value;
+    constexpr int U = R / Rs;
+    constexpr int T = N / R;
+    constexpr bool last = (Ns * Rs == N);
+    static_assert(R % Rs == 0, "stage radix must divide R");
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = t + u * T;
+      const int j = b & (Ns - 1);
+      Cx<Real> w[Rs];
+#pragma unroll
+      for (int r = 0; r < Rs; ++r) w[r] = v[u + r * U];
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < Rs; ++r) w[r] = w[r] * tw[j * r * (N / (Ns * Rs))];
+      }
+      dft<Real, Rs>(w);
+      if constexpr (last) {
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) v[u + r * U] = w[r];
+      } else {
+        const int base = (b / Ns) * Ns * Rs + j;
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) lds.store(base + r * Ns, w[r]);
+      }
+    }
+    if constexpr (!last) {
+      lds.sync();
+#pragma unroll
+      for (int e = 0; e < R; ++e) v[e] = lds.load(t + e * T);
+      lds.sync();
+      fft_stages<Real, N, R, Ns * Rs>(v, t, lds, tw);
+    }
+  }
+}
+
+template <typename Real, int N, int R, class Lds>
+__device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw) {
+  static_assert((N & (N - 1)) == 0 && N >= R, "N must be a power of two >= R");
+  fft_stages<Real, N, R, 1>(v, t, lds, tw);
+}
+
+// Forward FFT, multiply by ph[k] (which carries the 1/N of the inverse),
+// inverse FFT through conj(FFT(conj(.))).  ph is in natural k order.
+template <typename Real, int N, int R, class Lds>
+__device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw,
+                                               const Cx<Real>* __restrict__ ph) {
+  constexpr int T = N / R;
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = conj(v[e] * ph[t + e * T]);
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = conj(v[e]);
+}
+
+// ---------------------------------------------------------------------------
+// Exact local flow over tau of i d_t psi = (c0 n + c1 F.f) psi at one site.
+// n and F are constant along it, and with M = F.f one has M^3 = |F|^2 M, so
+//   exp(-i theta M) = 1 - i s M + c M^2,  theta = c1 tau,
+//   s = sin(|F| theta)/|F| = theta sinc(x/2) cos(x/2),
+//   c = (cos(|F| theta) - 1)/|F|^2 = -theta^2/2 sinc(x/2)^2,  x = |F| theta,
+// and the c0 part is the scalar phase exp(-i c0 n tau).  With g = F_+/sqrt2:
+//   (Mv)_{+1} = Fz v_{+1} + g* v_0,  (Mv)_0 = g v_{+1} + g* v_{-1},
+//   (Mv)_{-1} = g v_0 - Fz v_{-1}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+
+// sin(y)/y given sin(y); the series covers y -> 0
+template <typename Real>
+__device__ __forceinline__ Real sinc_of(Real y, Real sin_y) {
+  const Real thr = sizeof(Real) == 8 ? Real(1e-3) : Real(3e-2);
+  if (fabs(y) < thr) {
+    const Real y2 = y * y;
+    return Real(1) - y2 * (Real(1) / Real(6)) + y2 * y2 * (Real(1) / Real(120));
+  }
+  return sin_y / y;
+}
+
+template <typename Real>
+__device__ __forceinline__ void apply_M(const Cx<Real>* a, Cx<Real>* out, Cx<Real> g, Real fz) {
+  out[0] = scale(a[0], fz) + cmulc(g, a[1]);
+  out[1] = g * a[0] + cmulc(g, a[2]);
+  out[2] = g * a[1] - scale(a[2], fz);
+}
+
+template <typename Real>
+__device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, Real c1) {
+  const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
+  const Real n = d1 + d0 + dm;
+  const Cx<Real> g = cmulc(psi[0], psi[1]) + cmulc(psi[1], psi[2]);
+  const Real fz = d1 - dm;
+  const Real f2 = Real(2) * norm2(g) + fz * fz;
+  const Real theta = c1 * tau;
+  const Real half = Real(0.5) * sqrt(f2) * theta;
+  Real sh, ch;
+  sin_cos(half, &sh, &ch);
+  const Real sc = sinc_of(half, sh);
+  const Real s = theta * sc * ch;
+  const Real c = Real(-0.5) * theta * theta * sc * sc;
+  Cx<Real> phi[3], chi[3];
+  apply_M(psi, phi, g, fz);
+  apply_M(phi, chi, g, fz);
+  Real sp, cp;
+  sin_cos(c0 * n * tau, &sp, &cp);
+  const Cx<Real> ph = {cp, -sp};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    // psi - i s phi + c chi
+    const Cx<Real> u = {psi[m].re + s * phi[m].im + c * chi[m].re, psi[m].im - s * phi[m].re + c * chi[m].im};
+    psi[m] = ph * u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): two 64x64->128 multiplies per round,
+// Weyl key schedule.
+// ---------------------------------------------------------------------------
+struct U64x4 {
+  uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c.v[0]), lo0 = M0 * c.v[0];
+    const uint64_t hi1 = __umul64hi(M1, c.v[2]), lo1 = M1 * c.v[2];
+    U64x4 n;
+    n.v[0] = hi1 ^ c.v[1] ^ k0;
+    n.v[1] = lo1;
+    n.v[2] = hi0 ^ c.v[3] ^ k1;
+    n.v[3] = lo0;
+    c = n;
+  }
+  return c;
+}
+
+// (floor(x / 2^12) + 1/2) * 2^-52: exact, in (0, 1)
+__device__ __forceinline__ double open_unit(uint64_t x) { return (double(x >> 12) + 0.5) * 0x1p-52; }
+
+}  // namespace spin1

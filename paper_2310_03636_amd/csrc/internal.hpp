@@ -1,0 +1,72 @@
+// Internal interface between the C ABI (api.hip) and the kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace spin1 {
+
+// Geometry of one group: S samples of a dim-dimensional periodic grid,
+// field layout [S][3][Nz][Ny][Nx] (x fastest), n[a] = 1 for a >= dim.
+struct Geom {
+  int dim;
+  int n[3];
+  double dx;
+  int S;
+  int64_t sites;  // Nx * Ny * Nz
+  int64_t rows;   // sites / Nx: x-pencils per component and sample
+};
+
+// Number of strided-pass workgroups per (field, outer) and their column
+// width for axis length N (shared by host layout and launches).
+int spass_tx(int n, bool dbl);
+
+// Kernel modes
+enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3 };
+
+struct XPassArgs {
+  void* psi;        // field base [S][3][rows][Nx] (STEP, MEASURE, SF*)
+  void* out;        // SF: complex [S][rows][Nx]; SF_POWER: real [S][rows][Nx]
+  double* part;     // MEASURE: [S*rows][4] = (sum n, sum Fz, sum e_loc, sum e_kin_x)
+  const void* tw;   // exp(-2 pi i m / Nx)
+  const void* ph;   // [3][Nx] exp(-i (k^2/2 + q m^2) dt) / Nx
+  int64_t rows, sites;
+  int S;
+  double tau_pre, tau_post;  // local update before / after the kinetic step (0 = none)
+  double c0, c1, q;
+  double kscale;    // 2 pi / (Nx dx)
+  double power_scale;  // SF_POWER: 1 / N_sites
+};
+
+struct SPassArgs {
+  void* psi;        // field base
+  void* out;        // SF_POWER: real power array, same layout as psi (1 component)
+  double* part;     // MEASURE: one double per workgroup
+  const void* tw;   // exp(-2 pi i m / N)
+  const void* ph;   // [N] exp(-i k^2 dt / 2) / N
+  int64_t sa;       // element stride along the axis
+  int64_t inner;    // contiguous pencils per (field, outer)
+  int64_t outer;
+  int64_t outer_stride;
+  int64_t nfield;   // 3*S (STEP, MEASURE) or S (SF)
+  int64_t field_stride;
+  double kscale;
+  double power_scale;
+};
+
+hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,
+                         double dx);
+hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
+                       double n0, double wigner_var);
+hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a);
+hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a);
+hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
+hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
+                      const int32_t* offs, int nbins, double* out);
+hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,
+                             int64_t ny_blocks, const double* part_z, int64_t nz_blocks, double cell, double* obs);
+
+// x-pass pencils per workgroup for axis length n (host copy of the kernel config)
+int xpass_pencils(int n, bool dbl);
+
+}  // namespace spin1

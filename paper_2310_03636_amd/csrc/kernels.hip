@@ -1,0 +1,571 @@
+// HIP kernels of the spin-1 split-step library for gfx950 (MI355X).
+//
+// One time step of the symmetric split R(dt/2) [K Q](dt) R(dt/2) is a
+// sequence of streaming passes over the field [S][3][Nz][Ny][Nx]:
+//   x-pass  (contiguous pencils, all three components of a site in one
+//            thread): local update R(tau) -> FFT_x -> x-phase table (kinetic
+//            x part, quadratic Zeeman q m^2, 1/Nx) -> inverse FFT_x;
+//   y-, z-pass (strided pencils, one component per workgroup, a tile of TX
+//            adjacent columns so every row of the tile is one contiguous
+//            global segment): FFT -> axis phase table -> inverse FFT.
+// The kinetic operator factorises exactly over axes (the Laplacian is a sum
+// of per-axis second derivatives and the per-axis phases commute), so these
+// passes reproduce the d-dimensional Eq. (3) step.
+// The same pass skeletons also run forward-only transforms for the energy
+// (MODE_MEASURE) and for the transverse-spin spectrum (MODE_SF*).
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace spin1 {
+
+// --------------------------------------------------------------------------
+// launch configurations
+// --------------------------------------------------------------------------
+template <int N, typename Real>
+struct XCfg {
+  // radix 16 only where 3 x 16 single-precision values per thread still fit
+  static constexpr int R = N <= 8 ? N : ((N <= 1024 || sizeof(Real) == 8) ? 8 : 16);
+  static constexpr int T = N / R;
+  static constexpr int P = T >= 128 ? 1 : 128 / T;
+  static constexpr int THREADS = T * P;
+};
+
+template <int N, typename Real>
+struct SCfg {
+  static constexpr int R = N <= 8 ? N : (N <= 128 ? 8 : 16);
+  static constexpr int T = N / R;
+  static constexpr int CB = int(sizeof(Cx<Real>));
+  static constexpr int TXRAW = 65536 / (N * CB);
+  static constexpr int TX = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
+  static constexpr int THREADS = TX * T;
+};
+
+int xpass_pencils(int n, bool dbl) {
+  switch (n) {
+    case 8: return dbl ? XCfg<8, double>::P : XCfg<8, float>::P;
+    case 16: return dbl ? XCfg<16, double>::P : XCfg<16, float>::P;
+    case 32: return dbl ? XCfg<32, double>::P : XCfg<32, float>::P;
+    case 64: return dbl ? XCfg<64, double>::P : XCfg<64, float>::P;
+    case 128: return dbl ? XCfg<128, double>::P : XCfg<128, float>::P;
+    case 256: return dbl ? XCfg<256, double>::P : XCfg<256, float>::P;
+    case 512: return dbl ? XCfg<512, double>::P : XCfg<512, float>::P;
+    case 1024: return dbl ? XCfg<1024, double>::P : XCfg<1024, float>::P;
+    case 2048: return dbl ? XCfg<2048, double>::P : XCfg<2048, float>::P;
+    case 4096: return dbl ? XCfg<4096, double>::P : XCfg<4096, float>::P;
+  }
+  return 0;
+}
+
+template <typename Real>
+static int spass_tx_t(int n) {
+  switch (n) {
+    case 8: return SCfg<8, Real>::TX;
+    case 16: return SCfg<16, Real>::TX;
+    case 32: return SCfg<32, Real>::TX;
+    case 64: return SCfg<64, Real>::TX;
+    case 128: return SCfg<128, Real>::TX;
+    case 256: return SCfg<256, Real>::TX;
+    case 512: return SCfg<512, Real>::TX;
+    case 1024: return SCfg<1024, Real>::TX;
+  }
+  return 0;
+}
+
+int spass_tx(int n, bool dbl) { return dbl ? spass_tx_t<double>(n) : spass_tx_t<float>(n); }
+
+// --------------------------------------------------------------------------
+// LDS views used by the FFT stages
+// --------------------------------------------------------------------------
+template <typename Real>
+struct RowLds {
+  Cx<Real>* row;
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { row[i] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return row[i]; }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+template <typename Real, int TX>
+struct ColLds {
+  Cx<Real>* col;
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * TX] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * TX]; }
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// signed wavenumber index of DFT bin k
+template <int N>
+__device__ __forceinline__ int signed_k(int k) {
+  return k < N / 2 ? k : k - N;
+}
+
+// sum over the T consecutive lanes of a pencil (T a power of two <= 64)
+template <int T>
+__device__ __forceinline__ double lane_group_sum(double v) {
+#pragma unroll
+  for (int off = T / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// workgroup sum, fixed order; scratch must hold blockDim/64 doubles and may
+// alias LDS that is no longer in use.  Result valid in thread 0.  Workgroups
+// smaller than a wavefront shuffle only among their own lanes.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int width = blockDim.x < 64 ? int(blockDim.x) : 64;
+  for (int off = width / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) s += scratch[w];
+  return s;
+}
+
+// --------------------------------------------------------------------------
+// x-pass: contiguous pencils, all 3 components of each site in one thread
+// --------------------------------------------------------------------------
+template <typename Real, int N, int MODE>
+__global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a) {
+  using C = Cx<Real>;
+  constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
+  __shared__ C lds[P * N];
+  const int t = threadIdx.x % T;
+  const int p = threadIdx.x / T;
+  const int64_t pid = int64_t(blockIdx.x) * P + p;
+  const bool active = pid < int64_t(a.S) * a.rows;
+  const int64_t s = active ? pid / a.rows : 0;
+  const int64_t row = active ? pid - s * a.rows : 0;
+  RowLds<Real> L{lds + p * N};
+  const C* tw = static_cast<const C*>(a.tw);
+  C* base = static_cast<C*>(a.psi) + s * 3 * a.sites + row * N + t;
+
+  C v[3][R];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[m][e] = active ? base[m * a.sites + e * T] : C{Real(0), Real(0)};
+
+  if constexpr (MODE == MODE_STEP) {
+    const Real c0 = Real(a.c0), c1 = Real(a.c1);
+    if (a.tau_pre != 0.0) {
+      const Real tau = Real(a.tau_pre);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+    const C* ph = static_cast<const C*>(a.ph);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
+    if (a.tau_post != 0.0) {
+      const Real tau = Real(a.tau_post);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int e = 0; e < R; ++e) base[m * a.sites + e * T] = v[m][e];
+    }
+  } else if constexpr (MODE == MODE_MEASURE) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      const double d1 = double(norm2(v[0][e])), d0 = double(norm2(v[1][e])), dm = double(norm2(v[2][e]));
+      const C g = cmulc(v[0][e], v[1][e]) + cmulc(v[1][e], v[2][e]);
+      const double gre = double(g.re), gim = double(g.im);
+      const double n = d1 + d0 + dm, fz = d1 - dm;
+      const double f2 = 2.0 * (gre * gre + gim * gim) + fz * fz;
+      acc[0] += n;
+      acc[1] += fz;
+      acc[2] += 0.5 * a.c0 * n * n + 0.5 * a.c1 * f2 + a.q * (d1 + dm);
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      fft_pencil<Real, N, R>(v[m], t, L, tw);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const double kk = a.kscale * double(signed_k<N>(t + e * T));
+        acc[3] += 0.5 * kk * kk * double(norm2(v[m][e]));
+      }
+    }
+    acc[3] *= 1.0 / double(N);
+    double tot[4];
+    if constexpr (T <= 64) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tot[i] = lane_group_sum<T>(acc[i]);
+    } else {
+      constexpr int NW = T / 64;
+      double* scratch = reinterpret_cast<double*>(lds);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double w = lane_group_sum<64>(acc[i]);
+        if ((t & 63) == 0) scratch[(p * NW + (t >> 6)) * 4 + i] = w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double sacc = 0.0;
+        for (int w = 0; w < NW; ++w) sacc += scratch[(p * NW + w) * 4 + i];
+        tot[i] = sacc;
+      }
+    }
+    if (active && t == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a.part[pid * 4 + i] = tot[i];
+    }
+  } else {
+    // transverse spin F_perp = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1), forward FFT along x
+    const Real r2 = Real(1.41421356237309504880);
+    C f[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) f[e] = scale(cmulc(v[0][e], v[1][e]) + cmulc(v[1][e], v[2][e]), r2);
+    fft_pencil<Real, N, R>(f, t, L, tw);
+    if (active) {
+      const int64_t o = (s * a.rows + row) * N + t;
+      if constexpr (MODE == MODE_SF) {
+        C* out = static_cast<C*>(a.out) + o;
+#pragma unroll
+        for (int e = 0; e < R; ++e) out[e * T] = f[e];
+      } else {
+        Real* out = static_cast<Real*>(a.out) + o;
+        const Real ps = Real(a.power_scale);
+#pragma unroll
+        for (int e = 0; e < R; ++e) out[e * T] = norm2(f[e]) * ps;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// strided pass: TX adjacent pencils of one component, stride sa between
+// consecutive pencil elements
+// --------------------------------------------------------------------------
+template <typename Real, int N, int MODE>
+__global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a) {
+  using C = Cx<Real>;
+  constexpr int R = SCfg<N, Real>::R, T = SCfg<N, Real>::T, TX = SCfg<N, Real>::TX;
+  __shared__ C lds[N * TX];
+  const int c = threadIdx.x % TX;
+  const int t = threadIdx.x / TX;
+  const int64_t tiles = a.inner / TX;
+  int64_t wg = blockIdx.x;
+  const int64_t tile = wg % tiles;
+  wg /= tiles;
+  const int64_t o = wg % a.outer;
+  const int64_t f = wg / a.outer;
+  const int64_t off = f * a.field_stride + o * a.outer_stride + tile * TX + c;
+  C* base = static_cast<C*>(a.psi) + off;
+  ColLds<Real, TX> L{lds + c};
+  const C* tw = static_cast<const C*>(a.tw);
+
+  C v[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = base[int64_t(t + e * T) * a.sa];
+
+  if constexpr (MODE == MODE_STEP) {
+    fft_phase_ifft<Real, N, R>(v, t, L, tw, static_cast<const C*>(a.ph));
+#pragma unroll
+    for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
+  } else if constexpr (MODE == MODE_MEASURE) {
+    fft_pencil<Real, N, R>(v, t, L, tw);
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      const double kk = a.kscale * double(signed_k<N>(t + e * T));
+      acc += 0.5 * kk * kk * double(norm2(v[e]));
+    }
+    acc *= 1.0 / double(N);
+    const double tot = block_sum(acc, reinterpret_cast<double*>(lds));
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
+  } else if constexpr (MODE == MODE_SF) {
+    fft_pencil<Real, N, R>(v, t, L, tw);
+#pragma unroll
+    for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
+  } else {
+    fft_pencil<Real, N, R>(v, t, L, tw);
+    Real* out = static_cast<Real*>(a.out) + off;
+    const Real ps = Real(a.power_scale);
+#pragma unroll
+    for (int e = 0; e < R; ++e) out[int64_t(t + e * T) * a.sa] = norm2(v[e]) * ps;
+  }
+}
+
+// --------------------------------------------------------------------------
+// local update alone (closing half step of multi-dimensional grids)
+// --------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sites, Real tau, Real c0, Real c1) {
+  const int64_t total = int64_t(S) * sites;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    Cx<Real>* b = psi + s * 3 * sites + x;
+    Cx<Real> site[3] = {b[0], b[sites], b[2 * sites]};
+    local_update(site, tau, c0, c1);
+    b[0] = site[0];
+    b[sites] = site[1];
+    b[2 * sites] = site[2];
+  }
+}
+
+// --------------------------------------------------------------------------
+// phase and twiddle tables, computed in FP64 and rounded once
+// ph[m][k] = exp(-i (k^2/2 + q m^2) dt) / N (m = +1, 0, -1 when ncomp = 3)
+// tw[k]    = exp(-2 pi i k / N)
+// --------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_tables(Cx<Real>* ph, Cx<Real>* tw, int n, int ncomp, double dt, double q, double dx) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int js = k < n / 2 ? k : k - n;
+  const double kk = 2.0 * M_PI * double(js) / (double(n) * dx);
+  const double inv = 1.0 / double(n);
+  for (int c = 0; c < ncomp; ++c) {
+    const double m = ncomp == 3 ? double(1 - c) : 0.0;
+    const double ang = (0.5 * kk * kk + q * m * m) * dt;
+    double sn, cs;
+    sincos(ang, &sn, &cs);
+    ph[c * n + k] = Cx<Real>{Real(cs * inv), Real(-sn * inv)};
+  }
+  double sn, cs;
+  sincospi(-2.0 * double(k) / double(n), &sn, &cs);
+  tw[k] = Cx<Real>{Real(cs), Real(sn)};
+}
+
+// --------------------------------------------------------------------------
+// Wigner initial state: psi_m = sqrt(n0) delta_{m0} + sqrt(w / (2 dx^d)) (g_re + i g_im),
+// (g_re, g_im) by Box-Muller from Philox4x64-10(counter = (site, m, sample, group), key = (seed, 0))
+// --------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void k_init(Cx<Real>* psi, int S, int64_t sites, uint64_t seed, uint64_t group,
+                                              double amp, double sqrt_n0) {
+  const int64_t total = int64_t(S) * 3 * sites;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t x = i % sites;
+    const int64_t sc = i / sites;
+    const int64_t c = sc % 3, s = sc / 3;
+    U64x4 ctr;
+    ctr.v[0] = uint64_t(x);
+    ctr.v[1] = uint64_t(c);
+    ctr.v[2] = uint64_t(s);
+    ctr.v[3] = group;
+    const U64x4 r = philox4x64_10(ctr, seed, 0ull);
+    const double u1 = open_unit(r.v[0]), u2 = open_unit(r.v[1]);
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    double re = amp * rad * cs, im = amp * rad * sn;
+    if (c == 1) re += sqrt_n0;
+    psi[i] = Cx<Real>{Real(re), Real(im)};
+  }
+}
+
+// --------------------------------------------------------------------------
+// radial shells: one wavefront per (sample, shell), FP64 sum over the shell's
+// modes (listed in perm[offs[b] .. offs[b+1])), fixed order -> deterministic
+// --------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void k_bin(const Real* power, int64_t sites, const int32_t* perm,
+                                             const int32_t* offs, int nbins, double* out) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 4 + wave;
+  const int64_t s = blockIdx.y;
+  double acc = 0.0;
+  int lo = 0, hi = 0;
+  if (b < nbins) {
+    lo = offs[b];
+    hi = offs[b + 1];
+    const Real* ps = power + s * sites;
+    for (int i = lo + lane; i < hi; i += 64) acc += double(ps[perm[i]]);
+  }
+  acc = lane_group_sum<64>(acc);
+  if (b < nbins && lane == 0) out[s * nbins + b] = hi > lo ? acc / double(hi - lo) : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// observables: per sample (N, Fz, E) from the per-pencil / per-workgroup partials
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_obs_finish(const double* part_x, int64_t rows, const double* part_y,
+                                                    int64_t ny_blocks, const double* part_z, int64_t nz_blocks,
+                                                    double cell, double* obs) {
+  __shared__ double scratch[8];
+  const int64_t s = blockIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
+    for (int i = 0; i < 4; ++i) a[i] += part_x[(s * rows + r) * 4 + i];
+  double ek = 0.0;
+  if (part_y)
+    for (int64_t r = threadIdx.x; r < ny_blocks; r += blockDim.x) ek += part_y[s * ny_blocks + r];
+  if (part_z)
+    for (int64_t r = threadIdx.x; r < nz_blocks; r += blockDim.x) ek += part_z[s * nz_blocks + r];
+  double tot[5];
+  for (int i = 0; i < 4; ++i) tot[i] = block_sum(a[i], scratch);
+  tot[4] = block_sum(ek, scratch);
+  if (threadIdx.x == 0) {
+    obs[s * 3 + 0] = cell * tot[0];
+    obs[s * 3 + 1] = cell * tot[1];
+    obs[s * 3 + 2] = cell * (tot[2] + tot[3] + tot[4]);
+  }
+}
+
+// --------------------------------------------------------------------------
+// host launchers
+// --------------------------------------------------------------------------
+template <typename Real, int N, int MODE>
+static hipError_t xpass_n(hipStream_t st, const XPassArgs& a) {
+  constexpr int P = XCfg<N, Real>::P;
+  const int64_t pencils = int64_t(a.S) * a.rows;
+  const int64_t blocks = (pencils + P - 1) / P;
+  hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int MODE>
+static hipError_t xpass_mode(hipStream_t st, int n, const XPassArgs& a) {
+  switch (n) {
+    case 8: return xpass_n<Real, 8, MODE>(st, a);
+    case 16: return xpass_n<Real, 16, MODE>(st, a);
+    case 32: return xpass_n<Real, 32, MODE>(st, a);
+    case 64: return xpass_n<Real, 64, MODE>(st, a);
+    case 128: return xpass_n<Real, 128, MODE>(st, a);
+    case 256: return xpass_n<Real, 256, MODE>(st, a);
+    case 512: return xpass_n<Real, 512, MODE>(st, a);
+    case 1024: return xpass_n<Real, 1024, MODE>(st, a);
+    case 2048: return xpass_n<Real, 2048, MODE>(st, a);
+    case 4096: return xpass_n<Real, 4096, MODE>(st, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+static hipError_t xpass_t(hipStream_t st, int mode, int n, const XPassArgs& a) {
+  switch (mode) {
+    case MODE_STEP: return xpass_mode<Real, MODE_STEP>(st, n, a);
+    case MODE_MEASURE: return xpass_mode<Real, MODE_MEASURE>(st, n, a);
+    case MODE_SF: return xpass_mode<Real, MODE_SF>(st, n, a);
+    case MODE_SF_POWER: return xpass_mode<Real, MODE_SF_POWER>(st, n, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a) {
+  return dbl ? xpass_t<double>(st, mode, n, a) : xpass_t<float>(st, mode, n, a);
+}
+
+template <typename Real, int N, int MODE>
+static hipError_t spass_n(hipStream_t st, const SPassArgs& a) {
+  constexpr int TX = SCfg<N, Real>::TX;
+  if (a.inner % TX != 0) return hipErrorInvalidValue;
+  const int64_t blocks = a.nfield * a.outer * (a.inner / TX);
+  hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int MODE>
+static hipError_t spass_mode(hipStream_t st, int n, const SPassArgs& a) {
+  switch (n) {
+    case 8: return spass_n<Real, 8, MODE>(st, a);
+    case 16: return spass_n<Real, 16, MODE>(st, a);
+    case 32: return spass_n<Real, 32, MODE>(st, a);
+    case 64: return spass_n<Real, 64, MODE>(st, a);
+    case 128: return spass_n<Real, 128, MODE>(st, a);
+    case 256: return spass_n<Real, 256, MODE>(st, a);
+    case 512: return spass_n<Real, 512, MODE>(st, a);
+    case 1024: return spass_n<Real, 1024, MODE>(st, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename Real>
+static hipError_t spass_t(hipStream_t st, int mode, int n, const SPassArgs& a) {
+  switch (mode) {
+    case MODE_STEP: return spass_mode<Real, MODE_STEP>(st, n, a);
+    case MODE_MEASURE: return spass_mode<Real, MODE_MEASURE>(st, n, a);
+    case MODE_SF: return spass_mode<Real, MODE_SF>(st, n, a);
+    case MODE_SF_POWER: return spass_mode<Real, MODE_SF_POWER>(st, n, a);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a) {
+  return dbl ? spass_t<double>(st, mode, n, a) : spass_t<float>(st, mode, n, a);
+}
+
+static unsigned grid_for(int64_t work, int threads) {
+  int64_t b = (work + threads - 1) / threads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return unsigned(b);
+}
+
+hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,
+                         double dx) {
+  const unsigned blocks = unsigned((n + 255) / 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(ph),
+                       static_cast<Cx<double>*>(tw), n, ncomp, dt, q, dx);
+  else
+    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(ph),
+                       static_cast<Cx<float>*>(tw), n, ncomp, dt, q, dx);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group, double n0,
+                       double wigner_var) {
+  const double cell = g.dim == 1 ? g.dx : (g.dim == 2 ? g.dx * g.dx : g.dx * g.dx * g.dx);
+  const double amp = sqrt(wigner_var / (2.0 * cell));
+  const unsigned blocks = grid_for(int64_t(g.S) * 3 * g.sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_init<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), g.S, g.sites,
+                       seed, group, amp, sqrt(n0));
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), g.S, g.sites,
+                       seed, group, amp, sqrt(n0));
+  return hipGetLastError();
+}
+
+hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1) {
+  const unsigned blocks = grid_for(int64_t(S) * sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites, tau,
+                       c0, c1);
+  else
+    hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
+                       float(tau), float(c0), float(c1));
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
+                      const int32_t* offs, int nbins, double* out) {
+  const dim3 grid(unsigned((nbins + 3) / 4), unsigned(S));
+  if (dbl)
+    hipLaunchKernelGGL(k_bin<double>, grid, dim3(256), 0, st, static_cast<const double*>(power), sites, perm, offs,
+                       nbins, out);
+  else
+    hipLaunchKernelGGL(k_bin<float>, grid, dim3(256), 0, st, static_cast<const float*>(power), sites, perm, offs,
+                       nbins, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,
+                             int64_t ny_blocks, const double* part_z, int64_t nz_blocks, double cell, double* obs) {
+  hipLaunchKernelGGL(k_obs_finish, dim3(unsigned(S)), dim3(256), 0, st, part_x, rows, part_y, ny_blocks, part_z,
+                     nz_blocks, cell, obs);
+  return hipGetLastError();
+}
+
+}  // namespace spin1

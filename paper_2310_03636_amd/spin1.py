@@ -1,0 +1,305 @@
+"""Python binding of the spin-1 split-step C ABI (include/spin1.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libspin1.so``.  The functions below carry the C names without the
+``spin1_`` prefix and raise ``Spin1Error`` on a negative status.  ``Sim``
+bundles the device buffers (torch tensors used purely as device memory and a
+stream) for the common case.
+
+There is no CPU fallback: if the library is missing, loading fails loudly.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspin1.so")
+
+C64, C128 = 0, 1
+OK, EINVAL, EUNSUPPORTED, EHIP, ESTATE, ENOMEM = 0, -1, -2, -3, -4, -5
+
+FUNCTIONS = [
+    "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
+    "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
+    "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
+    "spin1_observables", "spin1_local_update", "spin1_profile_enable", "spin1_profile_read",
+    "spin1_last_error",
+]
+
+KERNEL_KINDS = ["xpass", "ypass", "zpass", "local", "spectrum", "shells", "observables", "other"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double),
+                ("samples", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("c0", ctypes.c_double), ("c1", ctypes.c_double), ("q", ctypes.c_double),
+                ("n0", ctypes.c_double), ("wigner_var", ctypes.c_double)]
+
+
+class Spin1Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("spin1 error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libspin1.so (built by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libspin1.so not found at %s: build it first (python -c "
+                          "'import __graft_entry__; __graft_entry__.build()')" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    gp, pp = ctypes.POINTER(Grid), ctypes.POINTER(Params)
+    sig = {
+        "spin1_create": (ctypes.c_int, [ctypes.POINTER(vp), i32, vp]),
+        "spin1_destroy": (ctypes.c_int, [vp]),
+        "spin1_check_grid": (ctypes.c_int, [gp, i32]),
+        "spin1_field_bytes": (sz, [gp, i32]),
+        "spin1_workspace_bytes": (sz, [gp, i32, i32]),
+        "spin1_num_bins": (i32, [gp]),
+        "spin1_bin_counts": (ctypes.c_int, [gp, ctypes.POINTER(i64)]),
+        "spin1_bind": (ctypes.c_int, [vp, gp, i32, pp, ctypes.POINTER(vp), vp]),
+        "spin1_init_wigner": (ctypes.c_int, [vp, ctypes.c_uint64, gp, i32, pp, ctypes.POINTER(vp), vp]),
+        "spin1_set_params": (ctypes.c_int, [vp, pp]),
+        "spin1_step": (ctypes.c_int, [vp, i64, f64]),
+        "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
+        "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
+        "spin1_local_update": (ctypes.c_int, [vp, f64]),
+        "spin1_profile_enable": (ctypes.c_int, [vp, i32]),
+        "spin1_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), i32]),
+        "spin1_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().spin1_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise Spin1Error(rc, last_error())
+    return rc
+
+
+def make_grid(dim, n, dx, samples):
+    """Grid(dim, (Nx[, Ny[, Nz]]), dx, samples); missing axes are 1."""
+    n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+    return Grid(int(dim), (ctypes.c_int32 * 3)(*n[:3]), float(dx), int(samples))
+
+
+def make_params(c0, c1, q, n0=1.0, wigner_var=0.5):
+    return Params(float(c0), float(c1), float(q), float(n0), float(wigner_var))
+
+
+def _grid_array(grids):
+    grids = list(grids)
+    arr = (Grid * len(grids))(*grids)
+    return arr, len(grids)
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*[ctypes.c_void_p(int(p)) for p in ptrs])
+
+
+# ---- thin wrappers with the C names -------------------------------------
+def create(dtype, stream=0):
+    h = ctypes.c_void_p()
+    _check(load().spin1_create(ctypes.byref(h), int(dtype), ctypes.c_void_p(int(stream) if stream else None)))
+    return h
+
+
+def destroy(ctx):
+    _check(load().spin1_destroy(ctx))
+
+
+def check_grid(grid, dtype):
+    _check(load().spin1_check_grid(ctypes.byref(grid), int(dtype)))
+
+
+def field_bytes(grid, dtype):
+    v = load().spin1_field_bytes(ctypes.byref(grid), int(dtype))
+    if v == 0:
+        raise Spin1Error(EINVAL, last_error())
+    return int(v)
+
+
+def workspace_bytes(grids, dtype):
+    arr, n = _grid_array(grids)
+    v = load().spin1_workspace_bytes(arr, n, int(dtype))
+    if v == 0:
+        raise Spin1Error(EINVAL, last_error())
+    return int(v)
+
+
+def num_bins(grid):
+    v = load().spin1_num_bins(ctypes.byref(grid))
+    if v < 0:
+        raise Spin1Error(v, last_error())
+    return int(v)
+
+
+def bin_counts(grid):
+    out = np.zeros(num_bins(grid), dtype=np.int64)
+    _check(load().spin1_bin_counts(ctypes.byref(grid), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+    return out
+
+
+def bind(ctx, grids, params, psi_ptrs, workspace_ptr):
+    arr, n = _grid_array(grids)
+    _check(load().spin1_bind(ctx, arr, n, ctypes.byref(params), _ptr_array(psi_ptrs),
+                             ctypes.c_void_p(int(workspace_ptr))))
+
+
+def init_wigner(ctx, seed, grids, params, psi_ptrs, workspace_ptr):
+    arr, n = _grid_array(grids)
+    _check(load().spin1_init_wigner(ctx, ctypes.c_uint64(int(seed)), arr, n, ctypes.byref(params),
+                                    _ptr_array(psi_ptrs), ctypes.c_void_p(int(workspace_ptr))))
+
+
+def set_params(ctx, params):
+    _check(load().spin1_set_params(ctx, ctypes.byref(params)))
+
+
+def step(ctx, n, dt):
+    _check(load().spin1_step(ctx, int(n), float(dt)))
+
+
+def structure_factor(ctx, group, bins_ptr):
+    _check(load().spin1_structure_factor(ctx, int(group), ctypes.c_void_p(int(bins_ptr))))
+
+
+def observables(ctx, group, obs_ptr):
+    _check(load().spin1_observables(ctx, int(group), ctypes.c_void_p(int(obs_ptr))))
+
+
+def local_update(ctx, tau):
+    _check(load().spin1_local_update(ctx, float(tau)))
+
+
+def profile_enable(ctx, enable=True):
+    _check(load().spin1_profile_enable(ctx, 1 if enable else 0))
+
+
+def profile_read(ctx):
+    """{kind: (total_ms, launches)} since the last read (synchronises the stream)."""
+    k = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    _check(load().spin1_profile_read(ctx, ms, cnt, k))
+    return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
+
+
+# ---- convenience owner of device buffers ---------------------------------
+def _spatial(grid):
+    return tuple(reversed([grid.n[a] for a in range(grid.dim)]))
+
+
+class Sim:
+    """Fields, workspace and a context for a list of groups on one GPU.
+
+    groups: list of (dim, (Nx, ...), dx, samples) tuples or Grid objects.
+    dtype: "c64" or "c128".  Torch supplies the device memory and the stream.
+    """
+
+    def __init__(self, groups, params, dtype="c64", device="cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.dtype_code = C64 if dtype in ("c64", C64, torch.complex64) else C128
+        self.cdtype = torch.complex64 if self.dtype_code == C64 else torch.complex128
+        self.grids = [g if isinstance(g, Grid) else make_grid(*g) for g in groups]
+        for g in self.grids:
+            check_grid(g, self.dtype_code)
+        self.params = params if isinstance(params, Params) else make_params(**params)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.psi = [torch.zeros((g.samples, 3) + _spatial(g), dtype=self.cdtype, device=self.device)
+                        for g in self.grids]
+            self.ws = torch.empty(workspace_bytes(self.grids, self.dtype_code), dtype=torch.uint8,
+                                  device=self.device)
+            self.ctx = create(self.dtype_code, self.stream.cuda_stream)
+        self.nbins = [num_bins(g) for g in self.grids]
+        self.bound = False
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            self.torch.cuda.synchronize(self.device)
+            destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self):
+        return [p.data_ptr() for p in self.psi]
+
+    def init_wigner(self, seed):
+        init_wigner(self.ctx, seed, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
+        self.bound = True
+
+    def set_fields(self, fields):
+        """Copy host or device arrays into the fields and bind them."""
+        torch = self.torch
+        for dst, src in zip(self.psi, fields):
+            src_t = torch.as_tensor(np.asarray(src) if not isinstance(src, torch.Tensor) else src)
+            dst.copy_(src_t.to(self.cdtype).reshape(dst.shape))
+        bind(self.ctx, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
+        self.bound = True
+
+    def set_params(self, params):
+        self.params = params if isinstance(params, Params) else make_params(**params)
+        set_params(self.ctx, self.params)
+
+    def step(self, n, dt):
+        step(self.ctx, n, dt)
+
+    def local_update(self, tau):
+        local_update(self.ctx, tau)
+
+    def fields(self):
+        """Synchronise and return the fields as numpy complex128 arrays."""
+        self.torch.cuda.synchronize(self.device)
+        return [p.cpu().numpy().astype(np.complex128) for p in self.psi]
+
+    def structure_factor_samples(self, group=0):
+        out = self.torch.empty((self.grids[group].samples, self.nbins[group]), dtype=self.torch.float64,
+                               device=self.device)
+        structure_factor(self.ctx, group, out.data_ptr())
+        return out
+
+    def structure_factor(self, group=0):
+        """(k_b, mean, se, counts, per-sample bins) for one group."""
+        per = self.structure_factor_samples(group).cpu().numpy()
+        g = self.grids[group]
+        s = per.shape[0]
+        mean = per.mean(axis=0)
+        se = per.std(axis=0, ddof=1) / math.sqrt(s) if s > 1 else np.zeros_like(mean)
+        nmax = max(g.n[a] for a in range(g.dim))
+        kb = np.arange(per.shape[1]) * 2.0 * math.pi / (nmax * g.dx)
+        return kb, mean, se, bin_counts(g), per
+
+    def observables(self, group=0):
+        out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
+        observables(self.ctx, group, out.data_ptr())
+        return out.cpu().numpy()

@@ -21,10 +21,25 @@ def gpu_available():
         return False
 
 
+def ensure_built():
+    """Load libspin1.so; compile it only when nothing is built yet."""
+    from paper_2310_03636_amd import spin1
+    if not os.path.exists(spin1.LIB_PATH):
+        from paper_2310_03636_amd import build_lib
+        build_lib.build()
+    spin1.load()
+    return spin1
+
+
+@pytest.fixture(scope="session")
+def abi():
+    """The binding with the library loaded (no device work)."""
+    return ensure_built()
+
+
 @pytest.fixture(scope="session")
 def lib():
     """The HIP library through its Python binding; GPU tests only."""
     if not gpu_available():
         pytest.skip("no GPU")
-    from paper_2310_03636_amd import spin1
-    return spin1
+    return ensure_built()

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 over all samples, components and sites, from
+identical initial fields): complex128 <= 1e-10 after 100 steps, complex64
+<= 1e-4 after 100 steps.  Single steps and transforms are held tighter.
+"""
+import numpy as np
+import pytest
+
+from oracle import spin1 as O
+from tests.inputs import random_field
+
+pytestmark = pytest.mark.gpu
+
+P1 = dict(c0=1.0, c1=-0.1, q=0.09, n0=1.0, wigner_var=0.5)
+P3 = dict(c0=1.0, c1=-0.05, q=0.025, n0=1.0, wigner_var=0.5)
+
+
+def oparams(p):
+    return O.Params(p["c0"], p["c1"], p["q"], p["n0"], p["wigner_var"])
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_gpu(lib, grid, p, dtype, psi0=None, seed=None, nsteps=0, dt=0.01):
+    sim = lib.Sim([grid], p, dtype=dtype)
+    if seed is not None:
+        sim.init_wigner(seed)
+    else:
+        sim.set_fields([psi0])
+    if nsteps:
+        sim.step(nsteps, dt)
+    return sim
+
+
+# ------------------------------------------------------------------ init
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 4), (2, (32, 16), 0.5, 3), (3, (16, 8, 8), 0.5, 2)])
+def test_init_wigner_matches_oracle(lib, grid):
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    ref = O.init_wigner(1001, og, oparams(P1))
+    sim = run_gpu(lib, grid, P1, "c128", seed=1001)
+    got = sim.fields()[0]
+    assert rel(got, ref) < 1e-14
+    sim32 = run_gpu(lib, grid, P1, "c64", seed=1001)
+    assert rel(sim32.fields()[0], ref) < 1e-7
+
+
+def test_init_wigner_groups_use_group_counter(lib):
+    grids = [(1, (64,), 0.5, 2), (2, (16, 16), 0.5, 2)]
+    sim = lib.Sim(grids, P1, dtype="c128")
+    sim.init_wigner(7)
+    f = sim.fields()
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        assert rel(f[gi], O.init_wigner(7, og, oparams(P1), group=gi)) < 1e-14
+
+
+# ------------------------------------------------------------------ one step, every size
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+def test_one_step_1d_all_sizes(lib, n):
+    grid = (1, (n,), 0.5, 5)
+    og = O.Grid(1, (n,), 0.5, 5)
+    psi0 = random_field(n, og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.01, oparams(P1), og)
+    got = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=1).fields()[0]
+    assert rel(got, ref) < 1e-13
+    got32 = run_gpu(lib, grid, P1, "c64", psi0=psi0, nsteps=1).fields()[0]
+    assert rel(got32, ref) < 2e-6
+
+
+@pytest.mark.parametrize("ny", [8, 16, 32, 64, 128, 256, 512, 1024])
+def test_one_step_2d_all_strided_sizes(lib, ny):
+    nx = 16
+    grid = (2, (nx, ny), 0.5, 2)
+    og = O.Grid(2, (nx, ny), 0.5, 2)
+    psi0 = random_field(ny + 1, og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(P1), og)
+    got = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=1, dt=0.02).fields()[0]
+    assert rel(got, ref) < 1e-13
+    got32 = run_gpu(lib, grid, P1, "c64", psi0=psi0, nsteps=1, dt=0.02).fields()[0]
+    assert rel(got32, ref) < 2e-6
+
+
+def test_one_step_3d_non_cubic(lib):
+    grid = (3, (32, 16, 8), 0.5, 2)
+    og = O.Grid(3, (32, 16, 8), 0.5, 2)
+    psi0 = random_field(3, og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(P3), og)
+    got = run_gpu(lib, grid, P3, "c128", psi0=psi0, nsteps=1, dt=0.02).fields()[0]
+    assert rel(got, ref) < 1e-13
+
+
+# ------------------------------------------------------------------ 100 steps
+@pytest.mark.parametrize("grid,p,dt", [
+    ((1, (256,), 0.5, 4), P1, 0.01),         # the 1D L=256 FP64 configuration
+    ((2, (64, 32), 0.5, 3), P1, 0.02),       # several tiles, ragged pencil count
+    ((3, (16, 16, 16), 0.5, 2), P3, 0.02),
+])
+def test_hundred_steps(lib, grid, p, dt):
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = O.init_wigner(1001, og, oparams(p))
+    ref = O.evolve(psi0, 100, dt, oparams(p), og)
+    got = run_gpu(lib, grid, p, "c128", seed=1001, nsteps=100, dt=dt).fields()[0]
+    assert rel(got, ref) < 1e-10
+    # complex64 starts from the rounded FP64 initial state
+    got32 = run_gpu(lib, grid, p, "c64", seed=1001, nsteps=100, dt=dt).fields()[0]
+    assert rel(got32, ref) < 1e-4
+
+
+def test_step_calls_compose(lib):
+    """n steps in one call equal the same steps split over several calls."""
+    grid = (2, (32, 32), 0.5, 2)
+    og = O.Grid(2, (32, 32), 0.5, 2)
+    psi0 = random_field(5, og.shape)
+    a = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=10, dt=0.02).fields()[0]
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0)
+    for k in (3, 1, 6):
+        sim.step(k, 0.02)
+    assert rel(sim.fields()[0], a) < 1e-13
+
+
+def test_time_reversal_on_gpu(lib):
+    grid = (2, (64, 64), 0.5, 2)
+    og = O.Grid(2, (64, 64), 0.5, 2)
+    psi0 = random_field(6, og.shape)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=50, dt=0.02)
+    sim.step(50, -0.02)
+    assert rel(sim.fields()[0], psi0) < 1e-12
+
+
+def test_zero_steps_is_identity(lib):
+    grid = (1, (64,), 0.5, 2)
+    og = O.Grid(1, (64,), 0.5, 2)
+    psi0 = random_field(8, og.shape)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0)
+    sim.step(0, 0.01)
+    assert np.array_equal(sim.fields()[0], psi0)
+
+
+def test_quench_set_params(lib):
+    grid = (1, (128,), 0.5, 2)
+    og = O.Grid(1, (128,), 0.5, 2)
+    psi0 = random_field(9, og.shape)
+    p2 = dict(P1, q=0.3)
+    ref = O.evolve(O.evolve(psi0, 5, 0.01, oparams(P1), og), 5, 0.01, oparams(p2), og)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=5)
+    sim.set_params(p2)
+    sim.step(5, 0.01)
+    assert rel(sim.fields()[0], ref) < 1e-12
+
+
+def test_local_update_matches_oracle(lib):
+    grid = (2, (16, 8), 0.5, 2)
+    og = O.Grid(2, (16, 8), 0.5, 2)
+    psi0 = random_field(10, og.shape, noise=1.0)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0)
+    sim.local_update(0.7)
+    assert rel(sim.fields()[0], O.local_flow(psi0, 0.7, P1["c0"], P1["c1"])) < 1e-13
+
+
+# ------------------------------------------------------------------ multiple groups
+def test_uneven_groups_step(lib):
+    grids = [(1, (4096,), 0.5, 3), (2, (32, 32), 0.5, 2), (2, (64, 16), 0.5, 1)]
+    sim = lib.Sim(grids, P1, dtype="c128")
+    sim.init_wigner(11)
+    sim.step(20, 0.02)
+    f = sim.fields()
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        ref = O.evolve(O.init_wigner(11, og, oparams(P1), group=gi), 20, 0.02, oparams(P1), og)
+        assert rel(f[gi], ref) < 1e-11
+
+
+# ------------------------------------------------------------------ structure factor
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 4), (2, (32, 64), 0.5, 3), (3, (16, 16, 8), 0.5, 2),
+                                  (1, (4096,), 0.5, 2), (2, (256, 256), 0.5, 1)])
+def test_structure_factor_matches_oracle(lib, grid):
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(12, og.shape, noise=0.5)
+    ref = O.structure_factor(psi0, og)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0)
+    got = sim.structure_factor_samples().cpu().numpy()
+    assert got.shape == ref.shape
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    sim32 = run_gpu(lib, grid, P1, "c64", psi0=psi0)
+    got32 = sim32.structure_factor_samples().cpu().numpy()
+    assert np.max(np.abs(got32 - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_structure_factor_deterministic(lib):
+    grid = (2, (64, 64), 0.5, 4)
+    sim = run_gpu(lib, grid, P1, "c64", seed=3)
+    a = sim.structure_factor_samples().cpu().numpy()
+    b = sim.structure_factor_samples().cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ observables
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 3), (2, (64, 32), 0.5, 2), (3, (16, 8, 16), 0.5, 2),
+                                  (1, (2048,), 0.5, 2)])
+def test_observables_match_oracle(lib, grid):
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(13, og.shape, noise=0.5)
+    ref = O.observables(psi0, oparams(P1), og)
+    got = run_gpu(lib, grid, P1, "c128", psi0=psi0).observables()
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    got32 = run_gpu(lib, grid, P1, "c64", psi0=psi0).observables()
+    assert np.allclose(got32, ref, rtol=2e-6, atol=2e-6 * np.abs(ref).max())
+
+
+def test_norm_and_fz_conserved_on_gpu(lib):
+    grid = (2, (128, 128), 0.5, 4)
+    sim = run_gpu(lib, grid, P1, "c64", seed=21)
+    o0 = sim.observables()
+    sim.step(200, 0.02)
+    o1 = sim.observables()
+    assert np.allclose(o1[:, 0], o0[:, 0], rtol=1e-5)
+    assert np.allclose(o1[:, 1], o0[:, 1], rtol=0, atol=1e-5 * o0[:, 0].max())
