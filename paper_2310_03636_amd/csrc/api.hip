@@ -138,12 +138,13 @@ void spass_geom(const Geom& g, int a, int64_t* sa, int64_t* inner, int64_t* oute
 
 size_t layout_group(const Geom& g, bool dbl, size_t base, Layout* L) {
   const size_t cb = dbl ? 16 : 8, rb = dbl ? 8 : 4;
+  const size_t tb = 16;  // table entry: complex128, or hi + lo complex64
   size_t off = base;
   for (int a = 0; a < g.dim; ++a) {
     L->ph[a] = off;
-    off = align_up(off + size_t(a == 0 ? 3 : 1) * g.n[a] * cb);
+    off = align_up(off + size_t(a == 0 ? 3 : 1) * g.n[a] * tb);
     L->tw[a] = off;
-    off = align_up(off + size_t(g.n[a]) * cb);
+    off = align_up(off + size_t(g.n[a]) * tb);
   }
   L->part[0] = off;
   off = align_up(off + size_t(g.S) * g.rows * 4 * sizeof(double));

@@ -39,6 +39,57 @@ template <typename Real>
 __device__ __forceinline__ Real norm2(Cx<Real> a) { return a.re * a.re + a.im * a.im; }
 
 // ---------------------------------------------------------------------------
+// Table entries (twiddles, phase factors).  They are computed in FP64; the
+// single-precision path keeps each value as an unevaluated sum hi + lo of two
+// floats, so a multiply by a table value carries no systematic rounding of
+// the constant (only the rounding of the result, which is unbiased).  A
+// rounded constant would repeat the same relative error in every step and the
+// errors would add up linearly over a run.
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct TabEntry;
+template <>
+struct alignas(16) TabEntry<float> {
+  float hr, hi, lr, li;
+};
+template <>
+struct alignas(16) TabEntry<double> {
+  double hr, hi;
+};
+
+__device__ __forceinline__ Cx<float> mul_tab(Cx<float> x, TabEntry<float> w) {
+  const float cre = x.re * w.lr - x.im * w.li;
+  const float cim = x.re * w.li + x.im * w.lr;
+  return {fmaf(x.re, w.hr, fmaf(-x.im, w.hi, cre)), fmaf(x.re, w.hi, fmaf(x.im, w.hr, cim))};
+}
+__device__ __forceinline__ Cx<double> mul_tab(Cx<double> x, TabEntry<double> w) {
+  return {x.re * w.hr - x.im * w.hi, x.re * w.hi + x.im * w.hr};
+}
+
+// x * (c_hi + c_lo) for a real constant given in FP64, compensated in FP32
+template <typename Real>
+__device__ __forceinline__ Real mul_const(Real x, double c) {
+  if constexpr (sizeof(Real) == 8) {
+    return x * c;
+  } else {
+    const float hi = float(c);
+    const float lo = float(c - double(hi));
+    return fmaf(x, hi, x * lo);
+  }
+}
+// x*c + y*s for FP64 constants c, s, compensated in FP32
+template <typename Real>
+__device__ __forceinline__ Real dot_const(Real x, double c, Real y, double s) {
+  if constexpr (sizeof(Real) == 8) {
+    return x * c + y * s;
+  } else {
+    const float ch = float(c), cl = float(c - double(ch));
+    const float sh = float(s), sl = float(s - double(sh));
+    return fmaf(x, ch, fmaf(y, sh, x * cl + y * sl));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // In-register DFT: out[k] = sum_r v[r] exp(-2 pi i r k / R), radix-2 split
 // into even and odd halves, constant twiddles specialised at compile time.
 // ---------------------------------------------------------------------------
@@ -60,23 +111,24 @@ __device__ constexpr double kSin16[8] = {0.0,
                                          0.70710678118654752440,
                                          0.38268343236508977173};
 
-// v * exp(-2 pi i K / R)
+// v * exp(-2 pi i K / R); the irrational constants go through mul_const /
+// dot_const so the single-precision path uses them at full FP64 accuracy
 template <typename Real, int R, int K>
 __device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v) {
   constexpr int I = K * (16 / R);
-  constexpr Real h = Real(0.70710678118654752440);
+  constexpr double h = 0.70710678118654752440;
   if constexpr (I == 0) {
     return v;
   } else if constexpr (I == 4) {
     return {v.im, -v.re};
   } else if constexpr (I == 2) {
-    return {h * (v.re + v.im), h * (v.im - v.re)};
+    return {mul_const<Real>(v.re + v.im, h), mul_const<Real>(v.im - v.re, h)};
   } else if constexpr (I == 6) {
-    return {h * (v.im - v.re), -h * (v.re + v.im)};
+    return {mul_const<Real>(v.im - v.re, h), -mul_const<Real>(v.re + v.im, h)};
   } else {
-    constexpr Real c = Real(kCos16[I]);
-    constexpr Real s = Real(kSin16[I]);
-    return {v.re * c + v.im * s, v.im * c - v.re * s};
+    constexpr double c = kCos16[I];
+    constexpr double s = kSin16[I];
+    return {dot_const<Real>(v.re, c, v.im, s), dot_const<Real>(v.im, c, v.re, -s)};
   }
 }
 
@@ -129,7 +181,7 @@ struct StageRadix {
 };
 
 template <typename Real, int N, int R, int Ns, class Lds>
-__device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw) {
   if constexpr (Ns < N) {
     constexpr int Rs = StageRadix<N, R, Ns>::value;
     constexpr int U = R / Rs;
@@ -145,7 +197,7 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const C
       for (int r = 0; r < Rs; ++r) w[r] = v[u + r * U];
       if constexpr (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < Rs; ++r) w[r] = w[r] * tw[j * r * (N / (Ns * Rs))];
+        for (int r = 1; r < Rs; ++r) w[r] = mul_tab(w[r], tw[j * r * (N / (Ns * Rs))]);
       }
       dft<Real, Rs>(w);
       if constexpr (last) {
@@ -168,7 +220,7 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const C
 }
 
 template <typename Real, int N, int R, class Lds>
-__device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw) {
+__device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw) {
   static_assert((N & (N - 1)) == 0 && N >= R, "N must be a power of two >= R");
   fft_stages<Real, N, R, 1>(v, t, lds, tw);
 }
@@ -176,12 +228,12 @@ __device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const C
 // Forward FFT, multiply by ph[k] (which carries the 1/N of the inverse),
 // inverse FFT through conj(FFT(conj(.))).  ph is in natural k order.
 template <typename Real, int N, int R, class Lds>
-__device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const Cx<Real>* __restrict__ tw,
-                                               const Cx<Real>* __restrict__ ph) {
+__device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw,
+                                               const TabEntry<Real>* __restrict__ ph) {
   constexpr int T = N / R;
   fft_pencil<Real, N, R>(v, t, lds, tw);
 #pragma unroll
-  for (int e = 0; e < R; ++e) v[e] = conj(v[e] * ph[t + e * T]);
+  for (int e = 0; e < R; ++e) v[e] = conj(mul_tab(v[e], ph[t + e * T]));
   fft_pencil<Real, N, R>(v, t, lds, tw);
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = conj(v[e]);
@@ -197,18 +249,37 @@ __device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, con
 //   (Mv)_{+1} = Fz v_{+1} + g* v_0,  (Mv)_0 = g v_{+1} + g* v_{-1},
 //   (Mv)_{-1} = g v_0 - Fz v_{-1}.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
-
-// sin(y)/y given sin(y); the series covers y -> 0
-template <typename Real>
-__device__ __forceinline__ Real sinc_of(Real y, Real sin_y) {
-  const Real thr = sizeof(Real) == 8 ? Real(1e-3) : Real(3e-2);
-  if (fabs(y) < thr) {
-    const Real y2 = y * y;
-    return Real(1) - y2 * (Real(1) / Real(6)) + y2 * y2 * (Real(1) / Real(120));
+// sin(y), cos(y) and sinc(y) = sin(y)/y.  Single precision: for |y| < pi/4
+// the Taylor series of sin(y)/y and cos(y) to order y^10 (remainder below
+// 2e-9 relative), otherwise the library sincosf and a quotient.  Double
+// precision: library sincos, with the Taylor series of sinc for tiny |y|.
+__device__ __forceinline__ void sincos_sinc(float y, float* s, float* c, float* sc) {
+  if (fabsf(y) < 0.78539816f) {
+    const float y2 = y * y;
+    float p = fmaf(y2, 1.0f / 39916800.0f, -1.0f / 362880.0f);
+    p = fmaf(y2, p, 1.0f / 5040.0f);
+    p = fmaf(y2, p, -1.0f / 120.0f);
+    p = fmaf(y2, p, 1.0f / 6.0f);
+    *sc = fmaf(-y2, p, 1.0f);
+    float q = fmaf(y2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+    q = fmaf(y2, q, -1.0f / 720.0f);
+    q = fmaf(y2, q, 1.0f / 24.0f);
+    q = fmaf(y2, q, -0.5f);
+    *c = fmaf(y2, q, 1.0f);
+    *s = y * *sc;
+  } else {
+    sincosf(y, s, c);
+    *sc = *s / y;
   }
-  return sin_y / y;
+}
+__device__ __forceinline__ void sincos_sinc(double y, double* s, double* c, double* sc) {
+  sincos(y, s, c);
+  if (fabs(y) < 1e-3) {
+    const double y2 = y * y;
+    *sc = 1.0 - y2 * (1.0 / 6.0) + y2 * y2 * (1.0 / 120.0);
+  } else {
+    *sc = *s / y;
+  }
 }
 
 template <typename Real>
@@ -227,16 +298,15 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
   const Real f2 = Real(2) * norm2(g) + fz * fz;
   const Real theta = c1 * tau;
   const Real half = Real(0.5) * sqrt(f2) * theta;
-  Real sh, ch;
-  sin_cos(half, &sh, &ch);
-  const Real sc = sinc_of(half, sh);
+  Real sh, ch, sc;
+  sincos_sinc(half, &sh, &ch, &sc);
   const Real s = theta * sc * ch;
   const Real c = Real(-0.5) * theta * theta * sc * sc;
   Cx<Real> phi[3], chi[3];
   apply_M(psi, phi, g, fz);
   apply_M(phi, chi, g, fz);
-  Real sp, cp;
-  sin_cos(c0 * n * tau, &sp, &cp);
+  Real sp, cp, unused;
+  sincos_sinc(c0 * n * tau, &sp, &cp, &unused);
   const Cx<Real> ph = {cp, -sp};
 #pragma unroll
   for (int m = 0; m < 3; ++m) {

@@ -138,7 +138,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
   const int64_t s = active ? pid / a.rows : 0;
   const int64_t row = active ? pid - s * a.rows : 0;
   RowLds<Real> L{lds + p * N};
-  const C* tw = static_cast<const C*>(a.tw);
+  const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
   C* base = static_cast<C*>(a.psi) + s * 3 * a.sites + row * N + t;
 
   C v[3][R];
@@ -160,7 +160,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
         v[2][e] = site[2];
       }
     }
-    const C* ph = static_cast<const C*>(a.ph);
+    const TabEntry<Real>* ph = static_cast<const TabEntry<Real>*>(a.ph);
 #pragma unroll
     for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
     if (a.tau_post != 0.0) {
@@ -271,14 +271,14 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
   const int64_t off = f * a.field_stride + o * a.outer_stride + tile * TX + c;
   C* base = static_cast<C*>(a.psi) + off;
   ColLds<Real, TX> L{lds + c};
-  const C* tw = static_cast<const C*>(a.tw);
+  const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
 
   C v[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = base[int64_t(t + e * T) * a.sa];
 
   if constexpr (MODE == MODE_STEP) {
-    fft_phase_ifft<Real, N, R>(v, t, L, tw, static_cast<const C*>(a.ph));
+    fft_phase_ifft<Real, N, R>(v, t, L, tw, static_cast<const TabEntry<Real>*>(a.ph));
 #pragma unroll
     for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
   } else if constexpr (MODE == MODE_MEASURE) {
@@ -323,12 +323,18 @@ __global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sit
 }
 
 // --------------------------------------------------------------------------
-// phase and twiddle tables, computed in FP64 and rounded once
+// phase and twiddle tables, computed in FP64 (hi + lo floats in single precision)
 // ph[m][k] = exp(-i (k^2/2 + q m^2) dt) / N (m = +1, 0, -1 when ncomp = 3)
 // tw[k]    = exp(-2 pi i k / N)
 // --------------------------------------------------------------------------
+__device__ __forceinline__ void store_tab(TabEntry<float>* p, double re, double im) {
+  const float hr = float(re), hi = float(im);
+  *p = TabEntry<float>{hr, hi, float(re - double(hr)), float(im - double(hi))};
+}
+__device__ __forceinline__ void store_tab(TabEntry<double>* p, double re, double im) { *p = TabEntry<double>{re, im}; }
+
 template <typename Real>
-__global__ void k_tables(Cx<Real>* ph, Cx<Real>* tw, int n, int ncomp, double dt, double q, double dx) {
+__global__ void k_tables(TabEntry<Real>* ph, TabEntry<Real>* tw, int n, int ncomp, double dt, double q, double dx) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int js = k < n / 2 ? k : k - n;
@@ -339,11 +345,11 @@ __global__ void k_tables(Cx<Real>* ph, Cx<Real>* tw, int n, int ncomp, double dt
     const double ang = (0.5 * kk * kk + q * m * m) * dt;
     double sn, cs;
     sincos(ang, &sn, &cs);
-    ph[c * n + k] = Cx<Real>{Real(cs * inv), Real(-sn * inv)};
+    store_tab(ph + c * n + k, cs * inv, -sn * inv);
   }
   double sn, cs;
   sincospi(-2.0 * double(k) / double(n), &sn, &cs);
-  tw[k] = Cx<Real>{Real(cs), Real(sn)};
+  store_tab(tw + k, cs, sn);
 }
 
 // --------------------------------------------------------------------------
@@ -516,11 +522,11 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
                          double dx) {
   const unsigned blocks = unsigned((n + 255) / 256);
   if (dbl)
-    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(ph),
-                       static_cast<Cx<double>*>(tw), n, ncomp, dt, q, dx);
+    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<double>*>(ph),
+                       static_cast<TabEntry<double>*>(tw), n, ncomp, dt, q, dx);
   else
-    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(ph),
-                       static_cast<Cx<float>*>(tw), n, ncomp, dt, q, dx);
+    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<float>*>(ph),
+                       static_cast<TabEntry<float>*>(tw), n, ncomp, dt, q, dx);
   return hipGetLastError();
 }
 

@@ -1,8 +1,13 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Tolerances (relative L2 over all samples, components and sites, from
-identical initial fields): complex128 <= 1e-10 after 100 steps, complex64
-<= 1e-4 after 100 steps.  Single steps and transforms are held tighter.
+identical initial fields): complex128 <= 1e-10 after 100 steps; complex64
+<= 1e-4 after 100 steps, or 10x the single-precision floor of the dynamics
+where that floor is higher.  The floor is the oracle run in FP64 with its
+state rounded to complex64 after every step: no single-precision code can
+beat it, and chaotic configurations (the 3D one amplifies a 1e-8 change of
+the initial state ~7000-fold in 100 steps) put it above 1e-4.  Single steps
+and transforms are held tighter.
 """
 import numpy as np
 import pytest
@@ -106,7 +111,16 @@ def test_hundred_steps(lib, grid, p, dt):
     assert rel(got, ref) < 1e-10
     # complex64 starts from the rounded FP64 initial state
     got32 = run_gpu(lib, grid, p, "c64", seed=1001, nsteps=100, dt=dt).fields()[0]
-    assert rel(got32, ref) < 1e-4
+    assert rel(got32, ref) < max(1e-4, 10.0 * single_precision_floor(psi0, 100, dt, p, og, ref))
+
+
+def single_precision_floor(psi0, nsteps, dt, p, og, ref):
+    """Error of the oracle itself when its state is rounded to complex64
+    after every step (FP64 arithmetic otherwise)."""
+    cur = psi0.astype(np.complex64).astype(np.complex128)
+    for _ in range(nsteps):
+        cur = O.strang_step(cur, dt, oparams(p), og).astype(np.complex64).astype(np.complex128)
+    return rel(cur, ref)
 
 
 def test_step_calls_compose(lib):
