@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/spin1.h"
+#include "spin1.h"
 #include "internal.hpp"
 
 using namespace spin1;
@@ -59,6 +59,9 @@ int validate_grid(const spin1_grid* g, int32_t dtype) {
   }
   const int64_t sites = int64_t(g->n[0]) * g->n[1] * g->n[2];
   if (sites * g->samples * 3 > (int64_t(1) << 40)) return fail(SPIN1_EUNSUPPORTED, "field too large");
+  // one component of one sample is addressed with 32-bit byte offsets inside a pass
+  if (sites * (dtype == SPIN1_C128 ? 16 : 8) >= (int64_t(1) << 32))
+    return fail(SPIN1_EUNSUPPORTED, "one component of one sample exceeds 4 GiB");
   return SPIN1_OK;
 }
 

@@ -249,36 +249,79 @@ __device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, con
 //   (Mv)_{+1} = Fz v_{+1} + g* v_0,  (Mv)_0 = g v_{+1} + g* v_{-1},
 //   (Mv)_{-1} = g v_0 - Fz v_{-1}.
 // ---------------------------------------------------------------------------
-// sin(y), cos(y) and sinc(y) = sin(y)/y.  Single precision: for |y| < pi/4
-// the Taylor series of sin(y)/y and cos(y) to order y^10 (remainder below
-// 2e-9 relative), otherwise the library sincosf and a quotient.  Double
-// precision: library sincos, with the Taylor series of sinc for tiny |y|.
-__device__ __forceinline__ void sincos_sinc(float y, float* s, float* c, float* sc) {
-  if (fabsf(y) < 0.78539816f) {
-    const float y2 = y * y;
-    float p = fmaf(y2, 1.0f / 39916800.0f, -1.0f / 362880.0f);
-    p = fmaf(y2, p, 1.0f / 5040.0f);
-    p = fmaf(y2, p, -1.0f / 120.0f);
-    p = fmaf(y2, p, 1.0f / 6.0f);
-    *sc = fmaf(-y2, p, 1.0f);
-    float q = fmaf(y2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
-    q = fmaf(y2, q, -1.0f / 720.0f);
-    q = fmaf(y2, q, 1.0f / 24.0f);
-    q = fmaf(y2, q, -0.5f);
-    *c = fmaf(y2, q, 1.0f);
-    *s = y * *sc;
+// Series kernels on u = y^2 for |y| <= pi/4 (Taylor series, remainder below
+// 1e-10 relative): sinc(y) = sin(y)/y and cos(y).
+__device__ __forceinline__ float sinc_series(float u) {
+  float p = fmaf(u, 1.0f / 39916800.0f, -1.0f / 362880.0f);
+  p = fmaf(u, p, 1.0f / 5040.0f);
+  p = fmaf(u, p, -1.0f / 120.0f);
+  p = fmaf(u, p, 1.0f / 6.0f);
+  return fmaf(-u, p, 1.0f);
+}
+__device__ __forceinline__ float cos_series(float u) {
+  float q = fmaf(u, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  q = fmaf(u, q, -1.0f / 720.0f);
+  q = fmaf(u, q, 1.0f / 24.0f);
+  q = fmaf(u, q, -0.5f);
+  return fmaf(u, q, 1.0f);
+}
+
+struct SinCos {
+  float s, c;
+};
+
+// |y| > 1e5: FP64 library evaluation, out of line and returned by value so
+// that the hot path neither inlines it nor touches scratch memory.
+__device__ __noinline__ SinCos sincos_huge(float y) {
+  double s, c;
+  sincos(double(y), &s, &c);
+  return SinCos{float(s), float(c)};
+}
+
+// sin and cos of a float of any size: Cody-Waite reduction by pi/2 with a
+// three-part constant (remainder exact to ~1e-12 for |y| <= 1e5), series on
+// the remainder, quadrant swap.
+__device__ __forceinline__ SinCos sincos_reduced(float y) {
+  if (!(fabsf(y) <= 1.0e5f)) return sincos_huge(y);
+  constexpr double kPio2 = 1.57079632679489661923;
+  constexpr float c1 = float(kPio2);
+  constexpr float c2 = float(kPio2 - double(c1));
+  constexpr float c3 = float(kPio2 - double(c1) - double(c2));
+  const float k = rintf(y * float(0.63661977236758134308));
+  float r = fmaf(-k, c1, y);
+  r = fmaf(-k, c2, r);
+  r = fmaf(-k, c3, r);
+  const float u = r * r;
+  const float sr = r * sinc_series(u), cr = cos_series(u);
+  const int q = int(k) & 3;
+  const float s0 = (q & 1) ? cr : sr, c0 = (q & 1) ? sr : cr;
+  return SinCos{(q & 2) ? -s0 : s0, ((q + 1) & 2) ? -c0 : c0};
+}
+
+// sin(y), cos(y) from y itself (single precision)
+__device__ __forceinline__ void sincos_small(float y, float* s, float* c) {
+  const float u = y * y;
+  if (u < 0.61685028f) {  // |y| < pi/4
+    *s = y * sinc_series(u);
+    *c = cos_series(u);
   } else {
-    sincosf(y, s, c);
-    *sc = *s / y;
+    const SinCos r = sincos_reduced(y);
+    *s = r.s;
+    *c = r.c;
   }
 }
-__device__ __forceinline__ void sincos_sinc(double y, double* s, double* c, double* sc) {
-  sincos(y, s, c);
-  if (fabs(y) < 1e-3) {
-    const double y2 = y * y;
-    *sc = 1.0 - y2 * (1.0 / 6.0) + y2 * y2 * (1.0 / 120.0);
+
+// sinc(y) and cos(y) from u = y^2 >= 0 (single precision): no square root on
+// the common path
+__device__ __forceinline__ void sinc_cos_from_square(float u, float* sc, float* c) {
+  if (u < 0.61685028f) {
+    *sc = sinc_series(u);
+    *c = cos_series(u);
   } else {
-    *sc = *s / y;
+    const float y = sqrtf(u);
+    const SinCos r = sincos_reduced(y);
+    *c = r.c;
+    *sc = r.s / y;
   }
 }
 
@@ -297,16 +340,28 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
   const Real fz = d1 - dm;
   const Real f2 = Real(2) * norm2(g) + fz * fz;
   const Real theta = c1 * tau;
-  const Real half = Real(0.5) * sqrt(f2) * theta;
-  Real sh, ch, sc;
-  sincos_sinc(half, &sh, &ch, &sc);
+  // sc = sinc(x/2), ch = cos(x/2) with x = |F| theta
+  Real sc, ch, sp, cp;
+  if constexpr (sizeof(Real) == 4) {
+    sinc_cos_from_square(Real(0.25) * f2 * theta * theta, &sc, &ch);
+    sincos_small(c0 * n * tau, &sp, &cp);
+  } else {
+    const Real half = Real(0.5) * sqrt(f2) * theta;
+    Real sh;
+    sincos(half, &sh, &ch);
+    if (fabs(half) < 1e-3) {
+      const Real h2 = half * half;
+      sc = Real(1) - h2 * (Real(1) / Real(6)) + h2 * h2 * (Real(1) / Real(120));
+    } else {
+      sc = sh / half;
+    }
+    sincos(c0 * n * tau, &sp, &cp);
+  }
   const Real s = theta * sc * ch;
   const Real c = Real(-0.5) * theta * theta * sc * sc;
   Cx<Real> phi[3], chi[3];
   apply_M(psi, phi, g, fz);
   apply_M(phi, chi, g, fz);
-  Real sp, cp, unused;
-  sincos_sinc(c0 * n * tau, &sp, &cp, &unused);
   const Cx<Real> ph = {cp, -sp};
 #pragma unroll
   for (int m = 0; m < 3; ++m) {

@@ -36,6 +36,7 @@ struct XPassArgs {
   double c0, c1, q;
   double kscale;    // 2 pi / (Nx dx)
   double power_scale;  // SF_POWER: 1 / N_sites
+  int lg_rows;      // log2(rows), set by the launcher
 };
 
 struct SPassArgs {
@@ -52,6 +53,7 @@ struct SPassArgs {
   int64_t field_stride;
   double kscale;
   double power_scale;
+  int lg_tiles, lg_outer;  // log2 of (inner / TX) and of outer, set by the launcher
 };
 
 hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,

@@ -21,6 +21,8 @@ namespace spin1 {
 // --------------------------------------------------------------------------
 // launch configurations
 // --------------------------------------------------------------------------
+// x-pass: radix R, N/R threads per pencil, P pencils per workgroup; STREAM
+// selects the persistent prefetching kernel for the step pass.
 template <int N, typename Real>
 struct XCfg {
   // radix 16 only where 3 x 16 single-precision values per thread still fit
@@ -28,8 +30,12 @@ struct XCfg {
   static constexpr int T = N / R;
   static constexpr int P = T >= 128 ? 1 : 128 / T;
   static constexpr int THREADS = T * P;
+  // the streaming kernel keeps twiddles and the 3-component phase table in LDS
+  static constexpr int STREAM_LDS = P * (N + N / T) * int(sizeof(Cx<Real>)) + 4 * N * 16;
+  static constexpr bool STREAM = STREAM_LDS <= 96 * 1024;
 };
 
+// strided pass: radix R, TX adjacent columns per workgroup (TX x N/R threads)
 template <int N, typename Real>
 struct SCfg {
   static constexpr int R = N <= 8 ? N : (N <= 128 ? 8 : 16);
@@ -38,6 +44,7 @@ struct SCfg {
   static constexpr int TXRAW = 65536 / (N * CB);
   static constexpr int TX = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
   static constexpr int THREADS = TX * T;
+  static constexpr bool STREAM = true;
 };
 
 int xpass_pencils(int n, bool dbl) {
@@ -76,19 +83,48 @@ int spass_tx(int n, bool dbl) { return dbl ? spass_tx_t<double>(n) : spass_tx_t<
 // --------------------------------------------------------------------------
 // LDS views used by the FFT stages
 // --------------------------------------------------------------------------
-template <typename Real>
-struct RowLds {
-  Cx<Real>* row;
-  __device__ __forceinline__ void store(int i, Cx<Real> v) { row[i] = v; }
-  __device__ __forceinline__ Cx<Real> load(int i) const { return row[i]; }
-  __device__ __forceinline__ void sync() { __syncthreads(); }
+// One pencil per row with one padding element after every T = N/R elements.
+// Every index a thread touches in a non-final stage differs from its first
+// one by less than T within a block of T, so all LDS addresses of a thread are
+// one base plus compile-time offsets, and the padding still breaks up the
+// power-of-two strides of the early stages across banks.
+template <int N, int T>
+struct RowPad {
+  static constexpr int ROW = N + N / T;
+  __device__ static __forceinline__ int at(int i) { return i + i / T; }
 };
 
+// LDS ordering among the lanes of one wavefront: LDS instructions of a wave
+// execute in issue order, so the exchange only needs the compiler to keep the
+// stores before the loads (fences at wavefront scope around a wave barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE: every pencil lies inside one wavefront (N/R <= 64), so its exchanges
+// synchronise only that wavefront; otherwise the whole workgroup.
+template <typename Real, int N, int T, bool WAVE>
+struct RowLds {
+  Cx<Real>* row;
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { row[RowPad<N, T>::at(i)] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return row[RowPad<N, T>::at(i)]; }
+  __device__ __forceinline__ void sync() {
+    if constexpr (WAVE)
+      wave_sync();
+    else
+      __syncthreads();
+  }
+};
+
+// Column tiles: element i of column c at i * (TX + 1) + c; the odd row pitch
+// spreads rows that differ by a power of two over different banks.
 template <typename Real, int TX>
 struct ColLds {
   Cx<Real>* col;
-  __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * TX] = v; }
-  __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * TX]; }
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * (TX + 1)] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * (TX + 1)]; }
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -130,14 +166,14 @@ template <typename Real, int N, int MODE>
 __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a) {
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
-  __shared__ C lds[P * N];
+  __shared__ C lds[P * RowPad<N, T>::ROW];
   const int t = threadIdx.x % T;
   const int p = threadIdx.x / T;
   const int64_t pid = int64_t(blockIdx.x) * P + p;
   const bool active = pid < int64_t(a.S) * a.rows;
   const int64_t s = active ? pid / a.rows : 0;
   const int64_t row = active ? pid - s * a.rows : 0;
-  RowLds<Real> L{lds + p * N};
+  RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
   const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
   C* base = static_cast<C*>(a.psi) + s * 3 * a.sites + row * N + t;
 
@@ -259,7 +295,7 @@ template <typename Real, int N, int MODE>
 __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a) {
   using C = Cx<Real>;
   constexpr int R = SCfg<N, Real>::R, T = SCfg<N, Real>::T, TX = SCfg<N, Real>::TX;
-  __shared__ C lds[N * TX];
+  __shared__ C lds[N * (TX + 1)];
   const int c = threadIdx.x % TX;
   const int t = threadIdx.x / TX;
   const int64_t tiles = a.inner / TX;
@@ -304,6 +340,156 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
     for (int e = 0; e < R; ++e) out[int64_t(t + e * T) * a.sa] = norm2(v[e]) * ps;
   }
 }
+
+// --------------------------------------------------------------------------
+// Streaming (persistent) variants of the step passes.  A grid of about
+// (CUs x resident workgroups) walks the work items with a stride of gridDim.x;
+// while item i is transformed, the global loads of item i + gridDim.x are
+// already in flight, so HBM traffic overlaps the FFT arithmetic even at one or
+// two resident workgroups per CU.  Every item is owned by exactly one
+// workgroup, so reading the next item early sees the pre-pass state.
+// --------------------------------------------------------------------------
+// The twiddle and phase tables are staged in LDS once per workgroup: a global
+// load issued after the prefetch could only be consumed once the whole
+// prefetch had arrived (the vector-memory counter retires in order).
+template <typename Real, int N>
+__global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
+  using C = Cx<Real>;
+  constexpr int R = SCfg<N, Real>::R, T = SCfg<N, Real>::T, TX = SCfg<N, Real>::TX;
+  __shared__ C lds[N * (TX + 1)];
+  __shared__ TabEntry<Real> tw[N];
+  __shared__ TabEntry<Real> ph[N];
+  const int c = threadIdx.x % TX;
+  const int t = threadIdx.x / TX;
+  const int64_t tiles = a.inner / TX;
+  ColLds<Real, TX> L{lds + c};
+  {
+    const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
+    const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      tw[i] = gtw[i];
+      ph[i] = gph[i];
+    }
+    __syncthreads();
+  }
+  // item -> (field f, outer o, tile): shifts, all three extents are powers of two
+  char* psi = static_cast<char*>(a.psi);
+  const uint32_t lane_off = uint32_t((c + int64_t(t) * a.sa) * int64_t(sizeof(C)));
+  const uint32_t step_e = uint32_t(int64_t(T) * a.sa * int64_t(sizeof(C)));
+  auto tile_base = [&](int64_t item) -> char* {
+    const int64_t tile = item & (tiles - 1);
+    const int64_t rest = item >> a.lg_tiles;
+    const int64_t o = rest & (a.outer - 1), f = rest >> a.lg_outer;
+    return psi + (f * a.field_stride + o * a.outer_stride + tile * TX) * int64_t(sizeof(C));
+  };
+  int64_t item = blockIdx.x;
+  if (item >= items) return;
+  C nxt[R];
+  {
+    const char* src = tile_base(item);
+#pragma unroll
+    for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
+  }
+  for (; item < items; item += gridDim.x) {
+    C v[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[e] = nxt[e];
+    char* dst = tile_base(item);
+    const int64_t next = item + gridDim.x;
+    if (next < items) {
+      const char* src = tile_base(next);
+#pragma unroll
+      for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
+    }
+    fft_phase_ifft<Real, N, R>(v, t, L, tw, ph);
+#pragma unroll
+    for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
+  }
+}
+
+template <typename Real, int N, bool ENABLED = XCfg<N, Real>::STREAM>
+__global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
+ if constexpr (ENABLED) {
+  using C = Cx<Real>;
+  constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
+  __shared__ C lds[P * RowPad<N, T>::ROW];
+  __shared__ TabEntry<Real> stw[N];
+  __shared__ TabEntry<Real> ph[3 * N];
+  const int t = threadIdx.x % T;
+  const int p = threadIdx.x / T;
+  RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
+  {
+    const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
+    const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = gtw[i];
+    for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) ph[i] = gph[i];
+    __syncthreads();
+  }
+  C* psi = static_cast<C*>(a.psi);
+  const int64_t npen = int64_t(a.S) * a.rows;
+  const Real c0 = Real(a.c0), c1 = Real(a.c1);
+  // pencil pid: component m starts at ((s*3 + m) * sites + row * N); rows is a power of two
+  auto comp_base = [&](int64_t pid, int m) -> C* {
+    const int64_t s = pid >> a.lg_rows;
+    return psi + (s * 3 + m) * a.sites + (pid & (a.rows - 1)) * N;
+  };
+  auto load3 = [&](C (&dst)[3][R], int64_t pid) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const C* src = comp_base(pid, m);
+#pragma unroll
+      for (int e = 0; e < R; ++e) dst[m][e] = src[uint32_t(t + e * T)];
+    }
+  };
+  int64_t g = blockIdx.x;
+  if (g >= groups) return;
+  C nxt[3][R];
+  if (g * P + p < npen) load3(nxt, g * P + p);
+  for (; g < groups; g += gridDim.x) {
+    const int64_t pid = g * P + p;
+    const bool active = pid < npen;
+    C v[3][R];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int e = 0; e < R; ++e) v[m][e] = nxt[m][e];
+    const int64_t next = g + gridDim.x;
+    if (next < groups && next * P + p < npen) load3(nxt, next * P + p);
+    if (a.tau_pre != 0.0) {
+      const Real tau = Real(a.tau_pre);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, stw, ph + m * N);
+    if (a.tau_post != 0.0) {
+      const Real tau = Real(a.tau_post);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        C* dst = comp_base(pid, m);
+#pragma unroll
+        for (int e = 0; e < R; ++e) dst[uint32_t(t + e * T)] = v[m][e];
+      }
+    }
+  }
+}
+ }
 
 // --------------------------------------------------------------------------
 // local update alone (closing half step of multi-dimensional grids)
@@ -431,12 +617,49 @@ __global__ __launch_bounds__(256) void k_obs_finish(const double* part_x, int64_
 // --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
+[[maybe_unused]] static int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t(1) << (r + 1)) <= v) ++r;
+  return r;
+}
+
+// Number of compute units of the current device (cached per device).
+[[maybe_unused]] static int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+// Grid of a streaming kernel: resident workgroups per CU x CUs, capped by the work.
+template <class K>
+static int64_t stream_grid(K kernel, int threads, int64_t items) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const int64_t g = int64_t(per_cu) * device_cus();
+  return items < g ? items : g;
+}
+
 template <typename Real, int N, int MODE>
 static hipError_t xpass_n(hipStream_t st, const XPassArgs& a) {
   constexpr int P = XCfg<N, Real>::P;
   const int64_t pencils = int64_t(a.S) * a.rows;
   const int64_t blocks = (pencils + P - 1) / P;
-  hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
+  if constexpr (MODE == MODE_STEP && XCfg<N, Real>::STREAM) {
+    XPassArgs b = a;
+    b.lg_rows = ilog2(a.rows);
+    const int64_t grid = stream_grid(k_xpass_stream<Real, N>, XCfg<N, Real>::THREADS, blocks);
+    hipLaunchKernelGGL((k_xpass_stream<Real, N>), dim3(unsigned(grid)), dim3(XCfg<N, Real>::THREADS), 0, st, b,
+                       blocks);
+  } else {
+    hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -477,7 +700,16 @@ static hipError_t spass_n(hipStream_t st, const SPassArgs& a) {
   constexpr int TX = SCfg<N, Real>::TX;
   if (a.inner % TX != 0) return hipErrorInvalidValue;
   const int64_t blocks = a.nfield * a.outer * (a.inner / TX);
-  hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
+  if constexpr (MODE == MODE_STEP && SCfg<N, Real>::STREAM) {
+    SPassArgs b = a;
+    b.lg_tiles = ilog2(a.inner / TX);
+    b.lg_outer = ilog2(a.outer);
+    const int64_t grid = stream_grid(k_spass_stream<Real, N>, SCfg<N, Real>::THREADS, blocks);
+    hipLaunchKernelGGL((k_spass_stream<Real, N>), dim3(unsigned(grid)), dim3(SCfg<N, Real>::THREADS), 0, st, b,
+                       blocks);
+  } else {
+    hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
+  }
   return hipGetLastError();
 }
 
