@@ -28,10 +28,10 @@ struct XCfg {
   // radix 16 only where 3 x 16 single-precision values per thread still fit
   static constexpr int R = N <= 8 ? N : ((N <= 1024 || sizeof(Real) == 8) ? 8 : 16);
   static constexpr int T = N / R;
-  static constexpr int P = T >= 128 ? 1 : 128 / T;
+  static constexpr int P = T >= 256 ? 1 : 256 / T;
   static constexpr int THREADS = T * P;
-  // the streaming kernel keeps twiddles and the 3-component phase table in LDS
-  static constexpr int STREAM_LDS = P * (N + N / T) * int(sizeof(Cx<Real>)) + 4 * N * 16;
+  // the streaming kernel keeps twiddles and two phase tables in LDS
+  static constexpr int STREAM_LDS = P * (N + N / 16) * int(sizeof(Cx<Real>)) + 3 * N * 16;
   static constexpr bool STREAM = STREAM_LDS <= 96 * 1024;
 };
 
@@ -83,15 +83,13 @@ int spass_tx(int n, bool dbl) { return dbl ? spass_tx_t<double>(n) : spass_tx_t<
 // --------------------------------------------------------------------------
 // LDS views used by the FFT stages
 // --------------------------------------------------------------------------
-// One pencil per row with one padding element after every T = N/R elements.
-// Every index a thread touches in a non-final stage differs from its first
-// one by less than T within a block of T, so all LDS addresses of a thread are
-// one base plus compile-time offsets, and the padding still breaks up the
-// power-of-two strides of the early stages across banks.
+// One pencil per row with one padding element after every 16 (measured best
+// on gfx950 for the radix-8 exchanges: it breaks up the power-of-two strides
+// of the early stages across LDS banks).
 template <int N, int T>
 struct RowPad {
-  static constexpr int ROW = N + N / T;
-  __device__ static __forceinline__ int at(int i) { return i + i / T; }
+  static constexpr int ROW = N + N / 16;
+  __device__ static __forceinline__ int at(int i) { return i + (i >> 4); }
 };
 
 // LDS ordering among the lanes of one wavefront: LDS instructions of a wave
@@ -414,7 +412,8 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass_stream(XPass
   constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
   __shared__ C lds[P * RowPad<N, T>::ROW];
   __shared__ TabEntry<Real> stw[N];
-  __shared__ TabEntry<Real> ph[3 * N];
+  // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
+  __shared__ TabEntry<Real> ph[2 * N];
   const int t = threadIdx.x % T;
   const int p = threadIdx.x / T;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
@@ -422,7 +421,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass_stream(XPass
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
     for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = gtw[i];
-    for (int i = threadIdx.x; i < 3 * N; i += blockDim.x) ph[i] = gph[i];
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) ph[i] = gph[i];
     __syncthreads();
   }
   C* psi = static_cast<C*>(a.psi);
@@ -467,7 +466,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass_stream(XPass
       }
     }
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, stw, ph + m * N);
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, stw, ph + (m == 1 ? N : 0));
     if (a.tau_post != 0.0) {
       const Real tau = Real(a.tau_post);
 #pragma unroll
