@@ -50,7 +50,7 @@ def run_gpu(dtype, steps, warmup, profile):
 
     def bench_step():
         sim.step(w["split_steps"], w["dt"])
-        sim.structure_factor_samples()
+        sim.structure_factor_device()
 
     for _ in range(warmup):
         bench_step()
@@ -58,13 +58,14 @@ def run_gpu(dtype, steps, warmup, profile):
     if profile:
         spin1.profile_read(sim.ctx)  # clear
         spin1.profile_enable(sim.ctx, True)
+    # events on the library's stream (the Sim's own stream)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record()
+    start.record(sim.stream)
     for _ in range(steps):
         bench_step()
-    stop.record()
+    stop.record(sim.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = spin1.profile_read(sim.ctx) if profile else None
@@ -87,7 +88,7 @@ def fp32_vs_fp64_error():
         sim = spin1.Sim([grid], w["params"], dtype=dt)
         sim.init_wigner(w["seed"])
         sim.step(w["split_steps"], w["dt"])
-        torch.cuda.synchronize()
+        sim.synchronize()
         out.append(sim.psi[0].to(torch.complex128))
         sim.close()
     err = (torch.linalg.vector_norm(out[0] - out[1]) / torch.linalg.vector_norm(out[1])).item()
@@ -143,10 +144,17 @@ def main():
     per_step_site_steps = w["samples"] * sites * w["split_steps"]
     grid = (w["dim"], w["n"], w["samples"])
 
+    # timed region with per-kernel HIP events (direct launches)
     sim, wall, ev_ms, prof = run_gpu("c64", args.steps, args.warmup, profile=True)
     value = per_step_site_steps * args.steps / (ev_ms / 1e3)
     sim.close()
     del sim
+    torch.cuda.empty_cache()
+    # the same steps replayed from captured HIP graphs (no per-kernel events)
+    simg, wallg, evg_ms, _ = run_gpu("c64", args.steps, args.warmup, profile=False)
+    value_graph = per_step_site_steps * args.steps / (evg_ms / 1e3)
+    simg.close()
+    del simg
     torch.cuda.empty_cache()
 
     # dominant kernel and its live average duration
@@ -194,6 +202,7 @@ def main():
                      "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes},
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
         "hbm_algorithmic_GBps_whole_step": None,
+        "graph_replay": {"value": value_graph, "unit": "site-steps/s", "ms_per_step": evg_ms / args.steps},
         "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
                  "ms_per_step": ev64 / args.fp64_steps},
         "speedup_fp32_vs_fp64": value / value64,

@@ -138,6 +138,19 @@ SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
  * combined, q excluded). */
 SPIN1_API int spin1_local_update(spin1_ctx* ctx, double tau);
 
+/* Options (spin1_set_option).
+ * SPIN1_OPT_GRAPHS: 1 (default) = spin1_step captures the launches of an
+ *   n-step call into a HIP graph on first use and replays it for later calls
+ *   with the same (n, dt) and unchanged binding and couplings; 0 = launch each
+ *   kernel directly.  Graphs are never used while profiling is enabled or on
+ *   the NULL stream.  At most 8 graphs are kept per context (least recently
+ *   used first out); spin1_bind and spin1_set_params retire them.
+ * SPIN1_OPT_GRAPH_MAX_STEPS: longest step sequence in one graph (default
+ *   1024); longer calls run as consecutive chunks, each ending at a
+ *   synchronized time. */
+enum spin1_option { SPIN1_OPT_GRAPHS = 0, SPIN1_OPT_GRAPH_MAX_STEPS = 1 };
+SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
+
 /* Kernel kinds reported by the profiling hooks. */
 enum spin1_kernel_kind {
   SPIN1_K_XPASS = 0,       /* x-pass of a step (local update, FFT_x, phase, IFFT_x) */

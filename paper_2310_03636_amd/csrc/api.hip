@@ -188,6 +188,15 @@ struct ProfRecord {
   hipEvent_t start, stop;
 };
 
+struct GraphEntry {
+  int64_t n;
+  double dt;
+  uint64_t version;
+  uint64_t last_use;
+  hipGraphExec_t exec;
+};
+constexpr size_t kMaxGraphs = 8;
+
 struct spin1_ctx {
   int dtype = SPIN1_C64;
   bool dbl = false;
@@ -204,7 +213,18 @@ struct spin1_ctx {
   std::vector<hipEvent_t> ev_pool;  // created events, reused
   std::vector<ProfRecord> rec;      // records since the last read
   size_t ev_used = 0;
+  // captured step sequences: (steps, dt) of the current binding and couplings
+  bool use_graphs = true;
+  int64_t graph_max_steps = 1024;
+  uint64_t version = 0;  // bumped whenever a captured graph could go stale
+  uint64_t use_clock = 0;
+  std::vector<GraphEntry> graphs;
+  void drop_graphs() {
+    for (GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   ~spin1_ctx() {
+    drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -325,6 +345,78 @@ SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int6
   return a;
 }
 
+// The launches of n steps of dt: step 0 opens with R(dt/2), later steps
+// merge the previous closing half with their own opening half into R(dt); the
+// last step closes with R(dt/2) (x-pass epilogue in 1D, k_local otherwise).
+int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double pre = i == 0 ? 0.5 * dt : dt;
+    for (auto& G : ctx->groups) {
+      XPassArgs xa = xargs(ctx, G);
+      xa.tau_pre = pre;
+      xa.tau_post = (G.geo.dim == 1 && i == n - 1) ? 0.5 * dt : 0.0;
+      hipError_t e;
+      {
+        Prof pr(ctx, SPIN1_K_XPASS);
+        e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
+      }
+      if (e != hipSuccess) return hip_fail(e, "x-pass");
+      for (int a = 1; a < G.geo.dim; ++a) {
+        const SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
+        {
+          Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
+          e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
+        }
+        if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
+      }
+      if (G.geo.dim > 1 && i == n - 1) {
+        {
+          Prof pr(ctx, SPIN1_K_LOCAL);
+          e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1);
+        }
+        if (e != hipSuccess) return hip_fail(e, "closing local update");
+      }
+    }
+  }
+  return SPIN1_OK;
+}
+
+// Replay (capturing on first use) the graph of n steps of dt.
+int launch_graph(spin1_ctx* ctx, int64_t n, double dt) {
+  GraphEntry* hit = nullptr;
+  for (GraphEntry& g : ctx->graphs)
+    if (g.n == n && g.dt == dt && g.version == ctx->version) hit = &g;
+  if (!hit) {
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const int rc = enqueue_steps(ctx, n, dt);
+    e = hipStreamEndCapture(ctx->stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (ctx->graphs.size() >= kMaxGraphs) {  // evict the least recently used
+      size_t lru = 0;
+      for (size_t i = 1; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].last_use < ctx->graphs[lru].last_use) lru = i;
+      (void)hipGraphExecDestroy(ctx->graphs[lru].exec);
+      ctx->graphs.erase(ctx->graphs.begin() + long(lru));
+    }
+    ctx->graphs.push_back(GraphEntry{n, dt, ctx->version, 0, exec});
+    hit = &ctx->graphs.back();
+  }
+  hit->last_use = ++ctx->use_clock;
+  const hipError_t e = hipGraphLaunch(hit->exec, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SPIN1_OK;
+}
+
 int bind_impl(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const spin1_params* p,
               void* const* psi_dev, void* ws) {
   int rc = check_ctx(ctx, false);
@@ -354,6 +446,8 @@ int bind_impl(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const 
   ctx->p = *p;
   ctx->bound = true;
   ctx->tab_valid = false;
+  ctx->version++;
+  ctx->drop_graphs();
   for (auto& G : ctx->groups)
     if ((rc = upload_shells(ctx, G))) {
       ctx->bound = false;
@@ -458,6 +552,7 @@ int spin1_set_params(spin1_ctx* ctx, const spin1_params* p) {
   if ((rc = validate_params(p))) return rc;
   ctx->p = *p;
   ctx->tab_valid = false;
+  ctx->version++;
   return SPIN1_OK;
 }
 
@@ -469,34 +564,13 @@ int spin1_step(spin1_ctx* ctx, int64_t n, double dt) {
   if (n == 0 || dt == 0.0) return SPIN1_OK;
   if (!ctx->tab_valid || ctx->tab_dt != dt || ctx->tab_q != ctx->p.q)
     if ((rc = make_tables(ctx, dt))) return rc;
-  for (int64_t i = 0; i < n; ++i) {
-    const double pre = i == 0 ? 0.5 * dt : dt;
-    for (auto& G : ctx->groups) {
-      XPassArgs xa = xargs(ctx, G);
-      xa.tau_pre = pre;
-      xa.tau_post = (G.geo.dim == 1 && i == n - 1) ? 0.5 * dt : 0.0;
-      hipError_t e;
-      {
-        Prof pr(ctx, SPIN1_K_XPASS);
-        e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
-      }
-      if (e != hipSuccess) return hip_fail(e, "x-pass");
-      for (int a = 1; a < G.geo.dim; ++a) {
-        const SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
-        {
-          Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
-          e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
-        }
-        if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
-      }
-      if (G.geo.dim > 1 && i == n - 1) {
-        {
-          Prof pr(ctx, SPIN1_K_LOCAL);
-          e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1);
-        }
-        if (e != hipSuccess) return hip_fail(e, "closing local update");
-      }
-    }
+  const bool graphs = ctx->use_graphs && !ctx->prof && ctx->stream != nullptr;
+  if (!graphs) return enqueue_steps(ctx, n, dt);
+  // calls longer than the graph limit run as consecutive synchronised chunks
+  while (n > 0) {
+    const int64_t m = n < ctx->graph_max_steps ? n : ctx->graph_max_steps;
+    if ((rc = launch_graph(ctx, m, dt))) return rc;
+    n -= m;
   }
   return SPIN1_OK;
 }
@@ -573,6 +647,21 @@ int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
                         G.lay.nblk[1] / G.geo.S, pz, G.lay.nblk[2] / G.geo.S, cell_of(G.geo), obs_dev);
   if (e != hipSuccess) return hip_fail(e, "observables finish");
   return SPIN1_OK;
+}
+
+int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  switch (option) {
+    case SPIN1_OPT_GRAPHS:
+      ctx->use_graphs = value != 0;
+      return SPIN1_OK;
+    case SPIN1_OPT_GRAPH_MAX_STEPS:
+      if (value < 1) return fail(SPIN1_EINVAL, "graph step limit must be >= 1");
+      ctx->graph_max_steps = value;
+      return SPIN1_OK;
+  }
+  return fail(SPIN1_EINVAL, "unknown option %d", option);
 }
 
 int spin1_profile_enable(spin1_ctx* ctx, int32_t enable) {

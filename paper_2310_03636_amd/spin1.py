@@ -24,9 +24,11 @@ FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
     "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
-    "spin1_observables", "spin1_local_update", "spin1_profile_enable", "spin1_profile_read",
-    "spin1_last_error",
+    "spin1_observables", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
+    "spin1_profile_read", "spin1_last_error",
 ]
+
+OPT_GRAPHS, OPT_GRAPH_MAX_STEPS = 0, 1
 
 KERNEL_KINDS = ["xpass", "ypass", "zpass", "local", "spectrum", "shells", "observables", "other"]
 
@@ -76,6 +78,7 @@ def load():
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
         "spin1_local_update": (ctypes.c_int, [vp, f64]),
+        "spin1_set_option": (ctypes.c_int, [vp, i32, i64]),
         "spin1_profile_enable": (ctypes.c_int, [vp, i32]),
         "spin1_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), i32]),
         "spin1_last_error": (ctypes.c_char_p, []),
@@ -193,6 +196,10 @@ def local_update(ctx, tau):
     _check(load().spin1_local_update(ctx, float(tau)))
 
 
+def set_option(ctx, option, value):
+    _check(load().spin1_set_option(ctx, int(option), int(value)))
+
+
 def profile_enable(ctx, enable=True):
     _check(load().spin1_profile_enable(ctx, 1 if enable else 0))
 
@@ -215,7 +222,10 @@ class Sim:
     """Fields, workspace and a context for a list of groups on one GPU.
 
     groups: list of (dim, (Nx, ...), dx, samples) tuples or Grid objects.
-    dtype: "c64" or "c128".  Torch supplies the device memory and the stream.
+    dtype: "c64" or "c128".  Torch supplies the device memory and a stream
+    of its own (default priority); every torch operation of this object runs
+    on that stream, so the library's work and torch's copies stay ordered.
+    Methods that return host arrays synchronise that stream.
     """
 
     def __init__(self, groups, params, dtype="c64", device="cuda:0"):
@@ -229,19 +239,19 @@ class Sim:
         for g in self.grids:
             check_grid(g, self.dtype_code)
         self.params = params if isinstance(params, Params) else make_params(**params)
-        with torch.cuda.device(self.device):
-            self.stream = torch.cuda.current_stream(self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             self.psi = [torch.zeros((g.samples, 3) + _spatial(g), dtype=self.cdtype, device=self.device)
                         for g in self.grids]
             self.ws = torch.empty(workspace_bytes(self.grids, self.dtype_code), dtype=torch.uint8,
                                   device=self.device)
-            self.ctx = create(self.dtype_code, self.stream.cuda_stream)
+        self.ctx = create(self.dtype_code, self.stream.cuda_stream)
         self.nbins = [num_bins(g) for g in self.grids]
         self.bound = False
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
-            self.torch.cuda.synchronize(self.device)
+            self.stream.synchronize()
             destroy(self.ctx)
             self.ctx = None
 
@@ -254,6 +264,9 @@ class Sim:
     def _ptrs(self):
         return [p.data_ptr() for p in self.psi]
 
+    def synchronize(self):
+        self.stream.synchronize()
+
     def init_wigner(self, seed):
         init_wigner(self.ctx, seed, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
         self.bound = True
@@ -261,15 +274,19 @@ class Sim:
     def set_fields(self, fields):
         """Copy host or device arrays into the fields and bind them."""
         torch = self.torch
-        for dst, src in zip(self.psi, fields):
-            src_t = torch.as_tensor(np.asarray(src) if not isinstance(src, torch.Tensor) else src)
-            dst.copy_(src_t.to(self.cdtype).reshape(dst.shape))
+        with torch.cuda.stream(self.stream):
+            for dst, src in zip(self.psi, fields):
+                src_t = torch.as_tensor(np.asarray(src) if not isinstance(src, torch.Tensor) else src)
+                dst.copy_(src_t.to(self.cdtype).reshape(dst.shape))
         bind(self.ctx, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
         self.bound = True
 
     def set_params(self, params):
         self.params = params if isinstance(params, Params) else make_params(**params)
         set_params(self.ctx, self.params)
+
+    def set_option(self, option, value):
+        set_option(self.ctx, option, value)
 
     def step(self, n, dt):
         step(self.ctx, n, dt)
@@ -278,19 +295,29 @@ class Sim:
         local_update(self.ctx, tau)
 
     def fields(self):
-        """Synchronise and return the fields as numpy complex128 arrays."""
-        self.torch.cuda.synchronize(self.device)
-        return [p.cpu().numpy().astype(np.complex128) for p in self.psi]
+        """The fields as numpy complex128 arrays (synchronises)."""
+        with self.torch.cuda.stream(self.stream):
+            out = [p.cpu().numpy().astype(np.complex128) for p in self.psi]
+        return out
 
-    def structure_factor_samples(self, group=0):
-        out = self.torch.empty((self.grids[group].samples, self.nbins[group]), dtype=self.torch.float64,
-                               device=self.device)
+    def structure_factor_device(self, group=0):
+        """Per-sample shell means [S, n_bins] (FP64) on the device, enqueued on
+        this object's stream and returned without synchronising."""
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((self.grids[group].samples, self.nbins[group]), dtype=self.torch.float64,
+                                   device=self.device)
         structure_factor(self.ctx, group, out.data_ptr())
         return out
 
+    def structure_factor_samples(self, group=0):
+        """Per-sample shell means [S, n_bins] as a numpy array."""
+        out = self.structure_factor_device(group)
+        with self.torch.cuda.stream(self.stream):
+            return out.cpu().numpy()
+
     def structure_factor(self, group=0):
         """(k_b, mean, se, counts, per-sample bins) for one group."""
-        per = self.structure_factor_samples(group).cpu().numpy()
+        per = self.structure_factor_samples(group)
         g = self.grids[group]
         s = per.shape[0]
         mean = per.mean(axis=0)
@@ -300,6 +327,9 @@ class Sim:
         return kb, mean, se, bin_counts(g), per
 
     def observables(self, group=0):
-        out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
+        """Per-sample (N, F_z, E) [S, 3] as a numpy array."""
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
         observables(self.ctx, group, out.data_ptr())
-        return out.cpu().numpy()
+        with self.torch.cuda.stream(self.stream):
+            return out.cpu().numpy()

@@ -195,19 +195,19 @@ def test_structure_factor_matches_oracle(lib, grid):
     psi0 = random_field(12, og.shape, noise=0.5)
     ref = O.structure_factor(psi0, og)
     sim = run_gpu(lib, grid, P1, "c128", psi0=psi0)
-    got = sim.structure_factor_samples().cpu().numpy()
+    got = sim.structure_factor_samples()
     assert got.shape == ref.shape
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     sim32 = run_gpu(lib, grid, P1, "c64", psi0=psi0)
-    got32 = sim32.structure_factor_samples().cpu().numpy()
+    got32 = sim32.structure_factor_samples()
     assert np.max(np.abs(got32 - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
 def test_structure_factor_deterministic(lib):
     grid = (2, (64, 64), 0.5, 4)
     sim = run_gpu(lib, grid, P1, "c64", seed=3)
-    a = sim.structure_factor_samples().cpu().numpy()
-    b = sim.structure_factor_samples().cpu().numpy()
+    a = sim.structure_factor_samples()
+    b = sim.structure_factor_samples()
     assert np.array_equal(a, b)
 
 
@@ -232,3 +232,54 @@ def test_norm_and_fz_conserved_on_gpu(lib):
     o1 = sim.observables()
     assert np.allclose(o1[:, 0], o0[:, 0], rtol=1e-5)
     assert np.allclose(o1[:, 1], o0[:, 1], rtol=0, atol=1e-5 * o0[:, 0].max())
+
+
+# ------------------------------------------------------------------ graph replay
+def test_graph_replays_match_direct_launches(lib):
+    """Captured step sequences replay bit-identically to direct launches, with
+    eager work and synchronisation between the replays."""
+    grid = (2, (64, 32), 0.5, 3)
+    a = lib.Sim([grid], P1, dtype="c64")
+    b = lib.Sim([grid], P1, dtype="c64")
+    b.set_option(lib.OPT_GRAPHS, 0)
+    a.init_wigner(5)
+    b.init_wigner(5)
+    for rep in range(4):
+        a.step(10, 0.02)
+        b.step(10, 0.02)
+        fa, fb = a.fields()[0], b.fields()[0]
+        assert np.array_equal(fa, fb), "replay %d differs" % rep
+        # eager work between replays
+        assert np.array_equal(a.structure_factor_samples(), b.structure_factor_samples())
+        a.observables()
+    # a new dt and new couplings retire the old graphs
+    a.step(7, 0.01)
+    b.step(7, 0.01)
+    p2 = dict(P1, q=0.2)
+    a.set_params(p2)
+    b.set_params(p2)
+    a.step(10, 0.02)
+    b.step(10, 0.02)
+    assert np.array_equal(a.fields()[0], b.fields()[0])
+
+
+def test_graph_chunking_matches_split_calls(lib):
+    grid = (1, (256,), 0.5, 4)
+    a = lib.Sim([grid], P1, dtype="c128")
+    a.set_option(lib.OPT_GRAPH_MAX_STEPS, 4)
+    b = lib.Sim([grid], P1, dtype="c128")
+    b.set_option(lib.OPT_GRAPHS, 0)
+    a.init_wigner(6)
+    b.init_wigner(6)
+    a.step(10, 0.01)
+    for k in (4, 4, 2):
+        b.step(k, 0.01)
+    assert np.array_equal(a.fields()[0], b.fields()[0])
+
+
+def test_graph_option_validation(lib):
+    sim = lib.Sim([(1, (64,), 0.5, 1)], P1)
+    with pytest.raises(lib.Spin1Error):
+        sim.set_option(lib.OPT_GRAPH_MAX_STEPS, 0)
+    with pytest.raises(lib.Spin1Error):
+        sim.set_option(99, 1)
