@@ -138,6 +138,27 @@ SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
  * combined, q excluded). */
 SPIN1_API int spin1_local_update(spin1_ctx* ctx, double tau);
 
+/* Reverse mode (one bound group).  The caller owns a checkpoint array of
+ * ceil(n / every) fields and an adjoint workspace of
+ * spin1_adjoint_workspace_bytes bytes (every + 2 fields plus a few kB).
+ *
+ * spin1_forward_ckpt: like spin1_step(ctx, n, dt), run as chunks of `every`
+ *   steps; the field at the start of chunk c is copied to checkpoint c first.
+ *   On return the bound field is the final field psi_T.
+ * spin1_adjoint: given dL/dS_{s,b} (device [S][spin1_num_bins] FP64) for any
+ *   real loss L of the per-sample shell means S_{s,b} of psi_T (as returned by
+ *   spin1_structure_factor), computes the gradients of L with respect to the
+ *   initial field (grad_psi0_dev: a field, dL/dRe + i dL/dIm), q and c1
+ *   (grad_qc1_dev: 2 doubles) by reverse-mode differentiation of the discrete
+ *   split-step map.  It expects the bound field to be psi_T from
+ *   spin1_forward_ckpt with the same n, dt and every, and the same couplings;
+ *   the states inside each chunk are recomputed from its checkpoint.  The
+ *   bound field is left unchanged. */
+SPIN1_API size_t spin1_adjoint_workspace_bytes(const spin1_grid* g, int32_t dtype, int64_t every);
+SPIN1_API int spin1_forward_ckpt(spin1_ctx* ctx, int64_t n, double dt, int64_t every, void* ckpt_dev);
+SPIN1_API int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every, const void* ckpt_dev,
+                            const double* dL_dbins_dev, void* adj_ws_dev, void* grad_psi0_dev, double* grad_qc1_dev);
+
 /* Options (spin1_set_option).
  * SPIN1_OPT_GRAPHS: 1 (default) = spin1_step captures the launches of an
  *   n-step call into a HIP graph on first use and replays it for later calls

@@ -124,4 +124,4 @@ def gradients(psi0, q, c1, c0, target, k_cut, nsteps, dt, grid):
     tgt = torch.tensor(np.asarray(target), dtype=torch.float64)
     L = loss(p, tq, tc1, float(c0), tgt, k_cut, nsteps, dt, grid)
     L.backward()
-    return float(L), p.grad.numpy(), float(tq.grad), float(tc1.grad)
+    return float(L.detach()), p.grad.numpy(), float(tq.grad), float(tc1.grad)

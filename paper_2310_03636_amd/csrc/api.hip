@@ -159,10 +159,8 @@ size_t layout_group(const Geom& g, bool dbl, size_t base, Layout* L) {
     L->part[a] = off;
     off = align_up(off + size_t(L->nblk[a]) * sizeof(double));
   }
-  if (g.dim > 1) {
-    L->sff = off;
-    off = align_up(off + size_t(g.S) * g.sites * cb);
-  }
+  L->sff = off;  // complex spectrum scratch (also the reverse-mode seed in 1D)
+  off = align_up(off + size_t(g.S) * g.sites * cb);
   L->pow = off;
   off = align_up(off + size_t(g.S) * g.sites * rb);
   L->perm = off;
@@ -345,37 +343,48 @@ SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int6
   return a;
 }
 
-// The launches of n steps of dt: step 0 opens with R(dt/2), later steps
-// merge the previous closing half with their own opening half into R(dt); the
-// last step closes with R(dt/2) (x-pass epilogue in 1D, k_local otherwise).
+// The passes of step i of an n-step sequence of dt on one field: step 0 opens
+// with R(dt/2), later steps merge the previous closing half with their own
+// opening half into R(dt); the last step closes with R(dt/2) (x-pass epilogue
+// in 1D, k_local otherwise).  tau_open = tau_close = 0 gives the kinetic +
+// Zeeman passes alone, which the reverse sweep applies to the adjoint field.
+int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double dt, double tau_open,
+                       double tau_close) {
+  XPassArgs xa = xargs(ctx, G);
+  xa.psi = field;
+  xa.tau_pre = tau_open;
+  xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
+  hipError_t e;
+  {
+    Prof pr(ctx, SPIN1_K_XPASS);
+    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
+  }
+  if (e != hipSuccess) return hip_fail(e, "x-pass");
+  for (int a = 1; a < G.geo.dim; ++a) {
+    const SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
+    {
+      Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
+      e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
+    }
+    if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
+  }
+  if (G.geo.dim > 1 && tau_close != 0.0) {
+    {
+      Prof pr(ctx, SPIN1_K_LOCAL);
+      e = launch_local(ctx->stream, ctx->dbl, field, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "closing local update");
+  }
+  return SPIN1_OK;
+}
+
 int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
   for (int64_t i = 0; i < n; ++i) {
     const double pre = i == 0 ? 0.5 * dt : dt;
+    const double close = i == n - 1 ? 0.5 * dt : 0.0;
     for (auto& G : ctx->groups) {
-      XPassArgs xa = xargs(ctx, G);
-      xa.tau_pre = pre;
-      xa.tau_post = (G.geo.dim == 1 && i == n - 1) ? 0.5 * dt : 0.0;
-      hipError_t e;
-      {
-        Prof pr(ctx, SPIN1_K_XPASS);
-        e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
-      }
-      if (e != hipSuccess) return hip_fail(e, "x-pass");
-      for (int a = 1; a < G.geo.dim; ++a) {
-        const SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
-        {
-          Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
-          e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
-        }
-        if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
-      }
-      if (G.geo.dim > 1 && i == n - 1) {
-        {
-          Prof pr(ctx, SPIN1_K_LOCAL);
-          e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1);
-        }
-        if (e != hipSuccess) return hip_fail(e, "closing local update");
-      }
+      const int rc = enqueue_group_step(ctx, G, G.psi, dt, pre, close);
+      if (rc) return rc;
     }
   }
   return SPIN1_OK;
@@ -646,6 +655,138 @@ int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
   e = launch_obs_finish(ctx->stream, G.geo.S, reinterpret_cast<const double*>(at(ctx, G.lay.part[0])), G.geo.rows, py,
                         G.lay.nblk[1] / G.geo.S, pz, G.lay.nblk[2] / G.geo.S, cell_of(G.geo), obs_dev);
   if (e != hipSuccess) return hip_fail(e, "observables finish");
+  return SPIN1_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reverse mode
+// ---------------------------------------------------------------------------
+static size_t adj_layout(const Geom& g, bool dbl, int64_t every, size_t* seg, size_t* hbuf, size_t* part,
+                         size_t* acc) {
+  const size_t fb = size_t(g.S) * 3 * size_t(g.sites) * (dbl ? 16 : 8);
+  size_t off = 0;
+  *seg = off;
+  off = align_up(off + size_t(every + 1) * fb);
+  *hbuf = off;
+  off = align_up(off + fb);
+  *part = off;
+  off = align_up(off + size_t(adj_local_blocks(g.S, g.sites)) * 2 * sizeof(double));
+  *acc = off;
+  off = align_up(off + 2 * sizeof(double));
+  return off;
+}
+
+size_t spin1_adjoint_workspace_bytes(const spin1_grid* g, int32_t dtype, int64_t every) {
+  if (validate_grid(g, dtype)) return 0;
+  if (every < 1) {
+    fail(SPIN1_EINVAL, "checkpoint interval must be >= 1");
+    return 0;
+  }
+  size_t a, b, c, d;
+  return adj_layout(geom_of(g), dtype == SPIN1_C128, every, &a, &b, &c, &d);
+}
+
+static int check_adjoint_args(spin1_ctx* ctx, int64_t n, double dt, int64_t every) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (ctx->groups.size() != 1) return fail(SPIN1_EUNSUPPORTED, "reverse mode supports one bound group");
+  if (n < 1) return fail(SPIN1_EINVAL, "n must be >= 1");
+  if (every < 1) return fail(SPIN1_EINVAL, "checkpoint interval must be >= 1");
+  if (!isfinite(dt) || dt == 0.0) return fail(SPIN1_EINVAL, "dt must be finite and nonzero");
+  return SPIN1_OK;
+}
+
+int spin1_forward_ckpt(spin1_ctx* ctx, int64_t n, double dt, int64_t every, void* ckpt_dev) {
+  int rc = check_adjoint_args(ctx, n, dt, every);
+  if (rc) return rc;
+  if (!ckpt_dev) return fail(SPIN1_EINVAL, "ckpt_dev is NULL");
+  const GroupState& G = ctx->groups[0];
+  const size_t fb = size_t(G.geo.S) * 3 * size_t(G.geo.sites) * (ctx->dbl ? 16 : 8);
+  const int64_t nck = (n + every - 1) / every;
+  for (int64_t c = 0; c < nck; ++c) {
+    const hipError_t e = hipMemcpyAsync(static_cast<char*>(ckpt_dev) + size_t(c) * fb, G.psi, fb,
+                                        hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+    const int64_t m = (n - c * every) < every ? (n - c * every) : every;
+    if ((rc = spin1_step(ctx, m, dt))) return rc;
+  }
+  return SPIN1_OK;
+}
+
+int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every, const void* ckpt_dev,
+                  const double* dl_dbins_dev, void* adj_ws_dev, void* grad_psi0_dev, double* grad_qc1_dev) {
+  int rc = check_adjoint_args(ctx, n, dt, every);
+  if (rc) return rc;
+  if (!ckpt_dev || !dl_dbins_dev || !adj_ws_dev || !grad_psi0_dev || !grad_qc1_dev)
+    return fail(SPIN1_EINVAL, "a device pointer argument is NULL");
+  if (reinterpret_cast<uintptr_t>(adj_ws_dev) % 256) return fail(SPIN1_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (!ctx->tab_valid || ctx->tab_dt != dt || ctx->tab_q != ctx->p.q)
+    if ((rc = make_tables(ctx, dt))) return rc;
+  const GroupState& G = ctx->groups[0];
+  const Geom& g = G.geo;
+  const size_t fb = size_t(g.S) * 3 * size_t(g.sites) * (ctx->dbl ? 16 : 8);
+  size_t oseg, oh, opart, oacc;
+  adj_layout(g, ctx->dbl, every, &oseg, &oh, &opart, &oacc);
+  char* ws = static_cast<char*>(adj_ws_dev);
+  char* seg = ws + oseg;
+  void* H = ws + oh;
+  double* part = reinterpret_cast<double*>(ws + opart);
+  double* acc = reinterpret_cast<double*>(ws + oacc);
+  const int nblk = adj_local_blocks(g.S, g.sites);
+  hipStream_t st = ctx->stream;
+  hipError_t e;
+  void* sff = at(ctx, G.lay.sff);
+
+  // 1. spectrum Fhat of the final field
+  XPassArgs xa = xargs(ctx, G);
+  xa.out = sff;
+  if ((e = launch_xpass(st, ctx->dbl, MODE_SF, g.n[0], xa)) != hipSuccess) return hip_fail(e, "adjoint spectrum x");
+  for (int a = 1; a < g.dim; ++a) {
+    const SPassArgs sa = sargs(ctx, G, a, sff, g.S);
+    if ((e = launch_spass(st, ctx->dbl, MODE_SF, g.n[a], sa)) != hipSuccess) return hip_fail(e, "adjoint spectrum");
+  }
+  // 2. seed in spectral space and back to real space (H(F_perp) = DFT(H(Fhat)))
+  if ((e = launch_adj_spectrum(st, ctx->dbl, sff, g, reinterpret_cast<const int32_t*>(at(ctx, G.lay.offs)), G.nbins,
+                               dl_dbins_dev)) != hipSuccess)
+    return hip_fail(e, "adjoint spectral seed");
+  if ((e = launch_fft1_x(st, ctx->dbl, g.n[0], sff, at(ctx, G.lay.tw[0]), int64_t(g.S) * g.rows)) != hipSuccess)
+    return hip_fail(e, "adjoint x transform");
+  for (int a = 1; a < g.dim; ++a) {
+    const SPassArgs sa = sargs(ctx, G, a, sff, g.S);
+    if ((e = launch_spass(st, ctx->dbl, MODE_SF, g.n[a], sa)) != hipSuccess) return hip_fail(e, "adjoint transform");
+  }
+  // 3. H(psi_T) from H(F_perp)
+  if ((e = launch_adj_seed(st, ctx->dbl, G.psi, sff, H, g.S, g.sites)) != hipSuccess) return hip_fail(e, "adjoint seed");
+  if ((e = hipMemsetAsync(acc, 0, 2 * sizeof(double), st)) != hipSuccess) return hip_fail(e, "clear accumulators");
+
+  // 4. segments in reverse: recompute the states, then walk the steps backwards
+  const int64_t nck = (n + every - 1) / every;
+  for (int64_t c = nck - 1; c >= 0; --c) {
+    const int64_t len = (n - c * every) < every ? (n - c * every) : every;
+    e = hipMemcpyAsync(seg, static_cast<const char*>(ckpt_dev) + size_t(c) * fb, fb, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "segment copy");
+    for (int64_t j = 0; j < len; ++j) {
+      e = hipMemcpyAsync(seg + size_t(j + 1) * fb, seg + size_t(j) * fb, fb, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "segment copy");
+      if ((rc = enqueue_group_step(ctx, G, seg + size_t(j + 1) * fb, dt, 0.5 * dt, 0.5 * dt))) return rc;
+    }
+    for (int64_t j = len - 1; j >= 0; --j) {
+      e = launch_adj_local(st, ctx->dbl, true, seg + size_t(j + 1) * fb, H, g.S, g.sites, 0.5 * dt, ctx->p.c0,
+                           ctx->p.c1, dt, part);
+      if (e != hipSuccess) return hip_fail(e, "adjoint closing half");
+      if ((e = launch_adj_accum(st, part, nblk, acc)) != hipSuccess) return hip_fail(e, "adjoint accumulate");
+      if ((rc = enqueue_group_step(ctx, G, H, dt, 0.0, 0.0))) return rc;
+      e = launch_adj_local(st, ctx->dbl, false, seg + size_t(j) * fb, H, g.S, g.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1,
+                           dt, part);
+      if (e != hipSuccess) return hip_fail(e, "adjoint opening half");
+      if ((e = launch_adj_accum(st, part, nblk, acc)) != hipSuccess) return hip_fail(e, "adjoint accumulate");
+    }
+  }
+  // 5. outputs in the real-gradient convention
+  if ((e = launch_conj(st, ctx->dbl, H, grad_psi0_dev, int64_t(g.S) * 3 * g.sites)) != hipSuccess)
+    return hip_fail(e, "gradient output");
+  if ((e = hipMemcpyAsync(grad_qc1_dev, acc, 2 * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return hip_fail(e, "gradient output");
   return SPIN1_OK;
 }
 

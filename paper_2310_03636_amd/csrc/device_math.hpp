@@ -332,19 +332,13 @@ __device__ __forceinline__ void apply_M(const Cx<Real>* a, Cx<Real>* out, Cx<Rea
   out[2] = g * a[1] - scale(a[2], fz);
 }
 
+// s = theta sinc(x/2) cos(x/2) and c = -theta^2/2 sinc(x/2)^2 for x = |F| theta,
+// |F|^2 = f2, and the phase exp(-i c0 n tau) as (cos, sin) of c0 n tau.
 template <typename Real>
-__device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, Real c1) {
-  const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
-  const Real n = d1 + d0 + dm;
-  const Cx<Real> g = cmulc(psi[0], psi[1]) + cmulc(psi[1], psi[2]);
-  const Real fz = d1 - dm;
-  const Real f2 = Real(2) * norm2(g) + fz * fz;
-  const Real theta = c1 * tau;
-  // sc = sinc(x/2), ch = cos(x/2) with x = |F| theta
-  Real sc, ch, sp, cp;
+__device__ __forceinline__ void rotation_coeffs(Real f2, Real theta, Real* s, Real* c) {
+  Real sc, ch;
   if constexpr (sizeof(Real) == 4) {
     sinc_cos_from_square(Real(0.25) * f2 * theta * theta, &sc, &ch);
-    sincos_small(c0 * n * tau, &sp, &cp);
   } else {
     const Real half = Real(0.5) * sqrt(f2) * theta;
     Real sh;
@@ -355,10 +349,30 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
     } else {
       sc = sh / half;
     }
-    sincos(c0 * n * tau, &sp, &cp);
   }
-  const Real s = theta * sc * ch;
-  const Real c = Real(-0.5) * theta * theta * sc * sc;
+  *s = theta * sc * ch;
+  *c = Real(-0.5) * theta * theta * sc * sc;
+}
+
+template <typename Real>
+__device__ __forceinline__ void angle_sincos(Real a, Real* sn, Real* cs) {
+  if constexpr (sizeof(Real) == 4)
+    sincos_small(a, sn, cs);
+  else
+    sincos(a, sn, cs);
+}
+
+template <typename Real>
+__device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, Real c1) {
+  const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
+  const Real n = d1 + d0 + dm;
+  const Cx<Real> g = cmulc(psi[0], psi[1]) + cmulc(psi[1], psi[2]);
+  const Real fz = d1 - dm;
+  const Real f2 = Real(2) * norm2(g) + fz * fz;
+  const Real theta = c1 * tau;
+  Real s, c, sp, cp;
+  rotation_coeffs(f2, theta, &s, &c);
+  angle_sincos(c0 * n * tau, &sp, &cp);
   Cx<Real> phi[3], chi[3];
   apply_M(psi, phi, g, fz);
   apply_M(phi, chi, g, fz);
@@ -368,6 +382,140 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
     // psi - i s phi + c chi
     const Cx<Real> u = {psi[m].re + s * phi[m].im + c * chi[m].re, psi[m].im - s * phi[m].re + c * chi[m].im};
     psi[m] = ph * u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Vector-Jacobian product of the local update (reverse mode).  Gradients use
+// the real convention G = dL/dRe + i dL/dIm, so dL = Re<G, dpsi> with
+// <a, b> = sum conj(a) b.  For psi' = exp(-i c0 n tau) U psi with
+// U = 1 - i s M + c M^2, M = F.f, s = s(|F|), c = c(|F|):
+//   G_in = U^H Gt + 2 lambda_n psi + 2 (alpha M psi + (B.f) psi),
+//   Gt = exp(+i c0 n tau) G',  lambda_n = c0 tau Im<G', psi'>,
+//   alpha = sigma1 Im<Gt, M psi> + sigma2 Re<Gt, M^2 psi>,
+//   B_a = Re<Gt, f_a u> + c Re<M Gt, f_a psi>,  u = -i s psi + c M psi,
+// with sigma1 = s'(r)/r and sigma2 = c'(r)/r (r = |F|); n and F change with
+// psi (dn = 2 Re<psi, dpsi>, dF_a = 2 Re<f_a psi, dpsi>).  With x = r theta:
+//   sigma1 = theta^3 (x cos x - sin x) / x^3,
+//   sigma2 = theta^4 (2 - 2 cos x - x sin x) / x^4,
+// evaluated by their Taylor series for small x.
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct SpinOps {
+  // Re<a, f_a b> for a = x, y, z
+  __device__ static __forceinline__ void expect(const Cx<Real>* a, const Cx<Real>* b, Real* out) {
+    const Real h = Real(0.70710678118654752440);
+    // f_x b = h (b0, b+1 + b-1, b0); f_y b = h (-i b0, i (b+1 - b-1), i b0); f_z b = (b+1, 0, -b-1)
+    const Cx<Real> fx0 = scale(b[1], h), fx1 = scale(b[0] + b[2], h), fx2 = scale(b[1], h);
+    const Cx<Real> fy0 = {h * b[1].im, -h * b[1].re};
+    const Cx<Real> d = b[0] - b[2];
+    const Cx<Real> fy1 = {-h * d.im, h * d.re};
+    const Cx<Real> fy2 = {-h * b[1].im, h * b[1].re};
+    out[0] = cmulc(a[0], fx0).re + cmulc(a[1], fx1).re + cmulc(a[2], fx2).re;
+    out[1] = cmulc(a[0], fy0).re + cmulc(a[1], fy1).re + cmulc(a[2], fy2).re;
+    out[2] = cmulc(a[0], b[0]).re - cmulc(a[2], b[2]).re;
+  }
+  // (B.f) v for a real vector B
+  __device__ static __forceinline__ void apply(Real bx, Real by, Real bz, const Cx<Real>* v, Cx<Real>* out) {
+    const Real h = Real(0.70710678118654752440);
+    // B.f = [[bz, h(bx - i by), 0], [h(bx + i by), 0, h(bx - i by)], [0, h(bx + i by), -bz]]
+    const Cx<Real> lo = {h * bx, -h * by}, up = {h * bx, h * by};
+    out[0] = scale(v[0], bz) + lo * v[1];
+    out[1] = up * v[0] + lo * v[2];
+    out[2] = up * v[1] - scale(v[2], bz);
+  }
+};
+
+template <typename Real>
+__device__ __forceinline__ void sigma_coeffs(Real theta, Real x, Real* s1, Real* s2) {
+  const Real x2 = x * x;
+  const Real t3 = theta * theta * theta, t4 = t3 * theta;
+  if (fabs(x) < Real(0.5)) {
+    // sum_k (-1)^k 2k x^(2k-2) / (2k+1)!  and  sum_k (-1)^k (2k-2) x^(2k-4) / (2k)!
+    Real p = Real(-16.0 / 355687428096000.0);
+    p = p * x2 + Real(14.0 / 1307674368000.0);
+    p = p * x2 + Real(-12.0 / 6227020800.0);
+    p = p * x2 + Real(10.0 / 39916800.0);
+    p = p * x2 + Real(-8.0 / 362880.0);
+    p = p * x2 + Real(6.0 / 5040.0);
+    p = p * x2 + Real(-4.0 / 120.0);
+    p = p * x2 + Real(2.0 / 6.0);
+    *s1 = -t3 * p;
+    Real q = Real(14.0 / 20922789888000.0);
+    q = q * x2 + Real(-12.0 / 87178291200.0);
+    q = q * x2 + Real(10.0 / 479001600.0);
+    q = q * x2 + Real(-8.0 / 3628800.0);
+    q = q * x2 + Real(6.0 / 40320.0);
+    q = q * x2 + Real(-4.0 / 720.0);
+    q = q * x2 + Real(2.0 / 24.0);
+    *s2 = t4 * q;
+  } else {
+    Real sx, cx;
+    if constexpr (sizeof(Real) == 4) {
+      const SinCos r = sincos_reduced(x);
+      sx = r.s;
+      cx = r.c;
+    } else {
+      sincos(x, &sx, &cx);
+    }
+    const Real x3 = x2 * x;
+    *s1 = t3 * (x * cx - sx) / x3;
+    *s2 = t4 * (Real(2) - Real(2) * cx - x * sx) / (x3 * x);
+  }
+}
+
+// Gradient at the input psi of R(tau) from the gradient gout at its output
+// (psi' = R(tau) psi is passed in as pout).  Returns G_in in gin.
+template <typename Real>
+__device__ __forceinline__ void local_update_vjp(const Cx<Real>* psi, const Cx<Real>* pout, const Cx<Real>* gout,
+                                                 Cx<Real>* gin, Real tau, Real c0, Real c1) {
+  const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
+  const Real n = d1 + d0 + dm;
+  const Cx<Real> g = cmulc(psi[0], psi[1]) + cmulc(psi[1], psi[2]);
+  const Real fz = d1 - dm;
+  const Real f2 = Real(2) * norm2(g) + fz * fz;
+  const Real theta = c1 * tau;
+  const Real x = sqrt(f2) * theta;
+  Real s, c, sp, cp;
+  rotation_coeffs(f2, theta, &s, &c);
+  Real s1, s2;
+  sigma_coeffs(theta, x, &s1, &s2);
+  angle_sincos(c0 * n * tau, &sp, &cp);
+  // Gt = exp(+i c0 n tau) G'
+  Cx<Real> gt[3];
+  const Cx<Real> ph = {cp, sp};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) gt[m] = ph * gout[m];
+  // lambda_n = c0 tau Im<G', psi'>
+  Real im_gp = Real(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) im_gp += cmulc(gout[m], pout[m]).im;
+  const Real lam_n = c0 * tau * im_gp;
+  Cx<Real> phi[3], chi[3], mg[3], m2g[3];
+  apply_M(psi, phi, g, fz);
+  apply_M(phi, chi, g, fz);
+  apply_M(gt, mg, g, fz);
+  apply_M(mg, m2g, g, fz);
+  Real im_phi = Real(0), re_chi = Real(0);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    im_phi += cmulc(gt[m], phi[m]).im;
+    re_chi += cmulc(gt[m], chi[m]).re;
+  }
+  const Real alpha = s1 * im_phi + s2 * re_chi;
+  Cx<Real> u[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) u[m] = Cx<Real>{s * psi[m].im + c * phi[m].re, -s * psi[m].re + c * phi[m].im};
+  Real b1[3], b2[3];
+  SpinOps<Real>::expect(gt, u, b1);
+  SpinOps<Real>::expect(mg, psi, b2);
+  Cx<Real> bf[3];
+  SpinOps<Real>::apply(b1[0] + c * b2[0], b1[1] + c * b2[1], b1[2] + c * b2[2], psi, bf);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    // U^H Gt = Gt + i s M Gt + c M^2 Gt
+    const Cx<Real> uh = {gt[m].re - s * mg[m].im + c * m2g[m].re, gt[m].im + s * mg[m].re + c * m2g[m].im};
+    gin[m] = uh + scale(psi[m], Real(2) * lam_n) + scale(phi[m], Real(2) * alpha) + scale(bf[m], Real(2));
   }
 }
 

@@ -68,6 +68,17 @@ hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_
 hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,
                              int64_t ny_blocks, const double* part_z, int64_t nz_blocks, double cell, double* obs);
 
+// reverse mode
+hipError_t launch_fft1_x(hipStream_t st, bool dbl, int n, void* f, const void* tw, int64_t pencils);
+int adj_local_blocks(int S, int64_t sites);
+hipError_t launch_adj_local(hipStream_t st, bool dbl, bool close, const void* state, void* h, int S, int64_t sites,
+                            double tau, double c0, double c1, double dt, double* part);
+hipError_t launch_adj_accum(hipStream_t st, const double* part, int nblocks, double* acc);
+hipError_t launch_adj_spectrum(hipStream_t st, bool dbl, void* f, const Geom& g, const int32_t* offs, int nbins,
+                               const double* dl_dbins);
+hipError_t launch_adj_seed(hipStream_t st, bool dbl, const void* psi, const void* hf, void* h, int S, int64_t sites);
+hipError_t launch_conj(hipStream_t st, bool dbl, const void* in, void* out, int64_t n);
+
 // x-pass pencils per workgroup for axis length n (host copy of the kernel config)
 int xpass_pencils(int n, bool dbl);
 

@@ -614,6 +614,177 @@ __global__ __launch_bounds__(256) void k_obs_finish(const double* part_x, int64_
 }
 
 // --------------------------------------------------------------------------
+// Reverse mode.  The backward sweep carries H = conj(G), G = dL/dRe + i dL/dIm:
+// in this form the adjoint of the kinetic + Zeeman step K Q(dt) is K Q(dt)
+// itself (the phase exp(-i(|k|^2/2 + q m^2) dt) is even in k, so
+// (K Q(dt))^H G = conj(K Q(dt) conj(G))), and the forward pass kernels serve
+// unchanged.  Only the local update needs its own VJP kernel.
+// --------------------------------------------------------------------------
+// One forward transform along x of a one-component field [S][rows][Nx].
+template <typename Real, int N>
+__global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_fft1_x(Cx<Real>* f, const TabEntry<Real>* tw,
+                                                                   int64_t pencils) {
+  using C = Cx<Real>;
+  constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
+  __shared__ C lds[P * RowPad<N, T>::ROW];
+  const int t = threadIdx.x % T;
+  const int p = threadIdx.x / T;
+  const int64_t pid = int64_t(blockIdx.x) * P + p;
+  const bool active = pid < pencils;
+  RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
+  C* base = f + (active ? pid : 0) * N + t;
+  C v[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = active ? base[e * T] : C{Real(0), Real(0)};
+  fft_pencil<Real, N, R>(v, t, L, tw);
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) base[e * T] = v[e];
+  }
+}
+
+// Local-update VJP over a whole field.
+//  CLOSE (backward of a step's closing half): state = psi_{n+1} = R(tau) psi_b;
+//    H in = conj(G) at psi_{n+1}, H out = conj(G) at psi_b; adds
+//    tau Im<G, M psi_{n+1}> to dL/dc1 and dt sum_{m=+-1} Im<G_b, psi_b> to dL/dq.
+//  OPEN (backward of a step's opening half): state = psi_n, psi_a = R(tau) psi_n;
+//    H in = conj(G) at psi_a, H out = conj(G) at psi_n; adds tau Im<G, M psi_a>.
+// Per-block FP64 partials (dL/dq, dL/dc1) go to part[2 * blockIdx.x + {0, 1}].
+template <typename Real, bool CLOSE>
+__global__ __launch_bounds__(256) void k_adj_local(const Cx<Real>* __restrict__ state, Cx<Real>* __restrict__ h,
+                                                   int S, int64_t sites, Real tau, Real c0, Real c1, double dt,
+                                                   double* part) {
+  using C = Cx<Real>;
+  __shared__ double scratch[8];
+  const int64_t total = int64_t(S) * sites;
+  double dq = 0.0, dc1 = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    const int64_t o = s * 3 * sites + x;
+    C st[3] = {state[o], state[o + sites], state[o + 2 * sites]};
+    C gout[3] = {conj(h[o]), conj(h[o + sites]), conj(h[o + 2 * sites])};
+    C pin[3], pout[3];
+    if constexpr (CLOSE) {
+      // psi_b = R(-tau) psi_{n+1}
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        pin[m] = st[m];
+        pout[m] = st[m];
+      }
+      local_update(pin, -tau, c0, c1);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        pin[m] = st[m];
+        pout[m] = st[m];
+      }
+      local_update(pout, tau, c0, c1);
+    }
+    // dL/dc1 += tau Im<G_out, M psi_out>   (M is the same at input and output)
+    {
+      const Cx<Real> g = cmulc(pout[0], pout[1]) + cmulc(pout[1], pout[2]);
+      const Real fz = norm2(pout[0]) - norm2(pout[2]);
+      C mp[3];
+      apply_M(pout, mp, g, fz);
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) acc += double(cmulc(gout[m], mp[m]).im);
+      dc1 += double(tau) * acc;
+    }
+    C gin[3];
+    local_update_vjp(pin, pout, gout, gin, tau, c0, c1);
+    if constexpr (CLOSE) {
+      // q enters through exp(-i q m^2 dt) on m = +-1 in the step before: dt Im<G_b, psi_b>
+      dq += dt * (double(cmulc(gin[0], pin[0]).im) + double(cmulc(gin[2], pin[2]).im));
+    }
+    h[o] = conj(gin[0]);
+    h[o + sites] = conj(gin[1]);
+    h[o + 2 * sites] = conj(gin[2]);
+  }
+  const double tq = block_sum(dq, scratch);
+  const double tc = block_sum(dc1, scratch);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = tq;
+    part[2 * blockIdx.x + 1] = tc;
+  }
+}
+
+// acc[i] += sum_b part[2 b + i] (fixed order)
+__global__ __launch_bounds__(256) void k_adj_accum(const double* part, int nblocks, double* acc) {
+  __shared__ double scratch[8];
+  double a0 = 0.0, a1 = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    a0 += part[2 * b];
+    a1 += part[2 * b + 1];
+  }
+  const double t0 = block_sum(a0, scratch);
+  const double t1 = block_sum(a1, scratch);
+  if (threadIdx.x == 0) {
+    acc[0] += t0;
+    acc[1] += t1;
+  }
+}
+
+// shell of a mode (same rule as the host tables): b = floor((isqrt(4J) + 1) / 2)
+__device__ __forceinline__ int mode_shell(int64_t site, int dim, int n0, int n1, int n2) {
+  const int n[3] = {n0, n1, n2};
+  int nm = n0;
+  if (dim > 1 && n1 > nm) nm = n1;
+  if (dim > 2 && n2 > nm) nm = n2;
+  int64_t J = 0, rest = site;
+  for (int a = 0; a < dim; ++a) {
+    const int64_t j = rest % n[a];
+    rest /= n[a];
+    const int64_t js = (j < n[a] / 2 ? j : j - n[a]) * (nm / n[a]);
+    J += js * js;
+  }
+  int64_t r = int64_t(sqrt(double(4 * J)));
+  while (r > 0 && r * r > 4 * J) --r;
+  while ((r + 1) * (r + 1) <= 4 * J) ++r;
+  return int((r + 1) / 2);
+}
+
+// Seed of the backward sweep in spectral space: with P_s(k) = |Fhat_s(k)|^2 / N
+// and S_{s,b} the mean of P_s over shell b, H(Fhat) = 2 (dL/dS_{s,b} / count_b) conj(Fhat) / N.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_spectrum(Cx<Real>* f, int S, int64_t sites, int dim, int n0, int n1,
+                                                      int n2, const int32_t* offs, int nbins, const double* dl_dbins) {
+  const int64_t total = int64_t(S) * sites;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    const int b = mode_shell(x, dim, n0, n1, n2);
+    const double cnt = double(offs[b + 1] - offs[b]);
+    const double w = 2.0 * dl_dbins[s * nbins + b] / (cnt * double(sites));
+    f[i] = scale(conj(f[i]), Real(w));
+  }
+}
+
+// H(psi) from H(F_perp) (both conj of real gradients): F_perp = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1)
+//   H_1 = sqrt2 conj(H_F psi_0),  H_0 = sqrt2 (H_F conj(psi_1) + conj(H_F psi_-1)),  H_-1 = sqrt2 H_F conj(psi_0)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_adj_seed(const Cx<Real>* __restrict__ psi, const Cx<Real>* __restrict__ hf,
+                                                  Cx<Real>* __restrict__ h, int S, int64_t sites) {
+  const int64_t total = int64_t(S) * sites;
+  const Real r2 = Real(1.41421356237309504880);
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    const int64_t o = s * 3 * sites + x;
+    const Cx<Real> p1 = psi[o], p0 = psi[o + sites], pm = psi[o + 2 * sites];
+    const Cx<Real> H = hf[i];
+    h[o] = scale(conj(H * p0), r2);
+    h[o + sites] = scale(H * conj(p1) + conj(H * pm), r2);
+    h[o + 2 * sites] = scale(H * conj(p0), r2);
+  }
+}
+
+// out = conj(in), elementwise over n complex values
+template <typename Real>
+__global__ __launch_bounds__(256) void k_conj(const Cx<Real>* in, Cx<Real>* out, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = conj(in[i]);
+}
+
+// --------------------------------------------------------------------------
 // host launchers
 // --------------------------------------------------------------------------
 [[maybe_unused]] static int ilog2(int64_t v) {
@@ -802,6 +973,103 @@ hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_
                              int64_t ny_blocks, const double* part_z, int64_t nz_blocks, double cell, double* obs) {
   hipLaunchKernelGGL(k_obs_finish, dim3(unsigned(S)), dim3(256), 0, st, part_x, rows, part_y, ny_blocks, part_z,
                      nz_blocks, cell, obs);
+  return hipGetLastError();
+}
+
+
+template <typename Real, int N>
+static hipError_t fft1_n(hipStream_t st, void* f, const void* tw, int64_t pencils) {
+  constexpr int P = XCfg<N, Real>::P;
+  const int64_t blocks = (pencils + P - 1) / P;
+  hipLaunchKernelGGL((k_fft1_x<Real, N>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st,
+                     static_cast<Cx<Real>*>(f), static_cast<const TabEntry<Real>*>(tw), pencils);
+  return hipGetLastError();
+}
+
+template <typename Real>
+static hipError_t fft1_t(hipStream_t st, int n, void* f, const void* tw, int64_t pencils) {
+  switch (n) {
+    case 8: return fft1_n<Real, 8>(st, f, tw, pencils);
+    case 16: return fft1_n<Real, 16>(st, f, tw, pencils);
+    case 32: return fft1_n<Real, 32>(st, f, tw, pencils);
+    case 64: return fft1_n<Real, 64>(st, f, tw, pencils);
+    case 128: return fft1_n<Real, 128>(st, f, tw, pencils);
+    case 256: return fft1_n<Real, 256>(st, f, tw, pencils);
+    case 512: return fft1_n<Real, 512>(st, f, tw, pencils);
+    case 1024: return fft1_n<Real, 1024>(st, f, tw, pencils);
+    case 2048: return fft1_n<Real, 2048>(st, f, tw, pencils);
+    case 4096: return fft1_n<Real, 4096>(st, f, tw, pencils);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fft1_x(hipStream_t st, bool dbl, int n, void* f, const void* tw, int64_t pencils) {
+  return dbl ? fft1_t<double>(st, n, f, tw, pencils) : fft1_t<float>(st, n, f, tw, pencils);
+}
+
+int adj_local_blocks(int S, int64_t sites) { return int(grid_for(int64_t(S) * sites, 256)); }
+
+hipError_t launch_adj_local(hipStream_t st, bool dbl, bool close, const void* state, void* h, int S, int64_t sites,
+                            double tau, double c0, double c1, double dt, double* part) {
+  const unsigned blocks = grid_for(int64_t(S) * sites, 256);
+  if (dbl) {
+    if (close)
+      hipLaunchKernelGGL((k_adj_local<double, true>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const Cx<double>*>(state), static_cast<Cx<double>*>(h), S, sites, tau, c0, c1, dt,
+                         part);
+    else
+      hipLaunchKernelGGL((k_adj_local<double, false>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const Cx<double>*>(state), static_cast<Cx<double>*>(h), S, sites, tau, c0, c1, dt,
+                         part);
+  } else {
+    if (close)
+      hipLaunchKernelGGL((k_adj_local<float, true>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const Cx<float>*>(state), static_cast<Cx<float>*>(h), S, sites, float(tau),
+                         float(c0), float(c1), dt, part);
+    else
+      hipLaunchKernelGGL((k_adj_local<float, false>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<const Cx<float>*>(state), static_cast<Cx<float>*>(h), S, sites, float(tau),
+                         float(c0), float(c1), dt, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_accum(hipStream_t st, const double* part, int nblocks, double* acc) {
+  hipLaunchKernelGGL(k_adj_accum, dim3(1), dim3(256), 0, st, part, nblocks, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_spectrum(hipStream_t st, bool dbl, void* f, const Geom& g, const int32_t* offs, int nbins,
+                               const double* dl_dbins) {
+  const unsigned blocks = grid_for(int64_t(g.S) * g.sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_adj_spectrum<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(f), g.S,
+                       g.sites, g.dim, g.n[0], g.n[1], g.n[2], offs, nbins, dl_dbins);
+  else
+    hipLaunchKernelGGL(k_adj_spectrum<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(f), g.S,
+                       g.sites, g.dim, g.n[0], g.n[1], g.n[2], offs, nbins, dl_dbins);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(hipStream_t st, bool dbl, const void* psi, const void* hf, void* h, int S, int64_t sites) {
+  const unsigned blocks = grid_for(int64_t(S) * sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_adj_seed<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
+                       static_cast<const Cx<double>*>(hf), static_cast<Cx<double>*>(h), S, sites);
+  else
+    hipLaunchKernelGGL(k_adj_seed<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
+                       static_cast<const Cx<float>*>(hf), static_cast<Cx<float>*>(h), S, sites);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj(hipStream_t st, bool dbl, const void* in, void* out, int64_t n) {
+  const unsigned blocks = grid_for(n, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_conj<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(in),
+                       static_cast<Cx<double>*>(out), n);
+  else
+    hipLaunchKernelGGL(k_conj<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(in),
+                       static_cast<Cx<float>*>(out), n);
   return hipGetLastError();
 }
 

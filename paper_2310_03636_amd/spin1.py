@@ -25,7 +25,8 @@ FUNCTIONS = [
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
     "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
     "spin1_observables", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
-    "spin1_profile_read", "spin1_last_error",
+    "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
+    "spin1_last_error",
 ]
 
 OPT_GRAPHS, OPT_GRAPH_MAX_STEPS = 0, 1
@@ -79,6 +80,9 @@ def load():
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
         "spin1_local_update": (ctypes.c_int, [vp, f64]),
         "spin1_set_option": (ctypes.c_int, [vp, i32, i64]),
+        "spin1_adjoint_workspace_bytes": (sz, [gp, i32, i64]),
+        "spin1_forward_ckpt": (ctypes.c_int, [vp, i64, f64, i64, vp]),
+        "spin1_adjoint": (ctypes.c_int, [vp, i64, f64, i64, vp, vp, vp, vp, vp]),
         "spin1_profile_enable": (ctypes.c_int, [vp, i32]),
         "spin1_profile_read": (ctypes.c_int, [vp, ctypes.POINTER(f64), ctypes.POINTER(i64), i32]),
         "spin1_last_error": (ctypes.c_char_p, []),
@@ -213,6 +217,23 @@ def profile_read(ctx):
     return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
 
 
+def adjoint_workspace_bytes(grid, dtype, every):
+    v = load().spin1_adjoint_workspace_bytes(ctypes.byref(grid), int(dtype), int(every))
+    if v == 0:
+        raise Spin1Error(EINVAL, last_error())
+    return int(v)
+
+
+def forward_ckpt(ctx, n, dt, every, ckpt_ptr):
+    _check(load().spin1_forward_ckpt(ctx, int(n), float(dt), int(every), ctypes.c_void_p(int(ckpt_ptr))))
+
+
+def adjoint(ctx, n, dt, every, ckpt_ptr, dl_dbins_ptr, ws_ptr, grad_psi0_ptr, grad_qc1_ptr):
+    vp = ctypes.c_void_p
+    _check(load().spin1_adjoint(ctx, int(n), float(dt), int(every), vp(int(ckpt_ptr)), vp(int(dl_dbins_ptr)),
+                                vp(int(ws_ptr)), vp(int(grad_psi0_ptr)), vp(int(grad_qc1_ptr))))
+
+
 # ---- convenience owner of device buffers ---------------------------------
 def _spatial(grid):
     return tuple(reversed([grid.n[a] for a in range(grid.dim)]))
@@ -326,6 +347,29 @@ class Sim:
         kb = np.arange(per.shape[1]) * 2.0 * math.pi / (nmax * g.dx)
         return kb, mean, se, bin_counts(g), per
 
+    # ---- reverse mode (one group) ----
+    def forward_ckpt(self, n, dt, every):
+        """Advance n steps, keeping a checkpoint every `every` steps (device tensor)."""
+        torch = self.torch
+        nck = (int(n) + int(every) - 1) // int(every)
+        with torch.cuda.stream(self.stream):
+            ckpt = torch.empty((nck,) + tuple(self.psi[0].shape), dtype=self.cdtype, device=self.device)
+        forward_ckpt(self.ctx, n, dt, every, ckpt.data_ptr())
+        return ckpt
+
+    def adjoint(self, n, dt, every, ckpt, dl_dbins):
+        """(dL/dpsi0 field, tensor [dL/dq, dL/dc1]) for dL/dS_{s,b} = dl_dbins [S, n_bins]."""
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            dl = torch.as_tensor(dl_dbins, dtype=torch.float64).to(self.device).contiguous()
+            ws = torch.empty(adjoint_workspace_bytes(self.grids[0], self.dtype_code, every), dtype=torch.uint8,
+                             device=self.device)
+            grad = torch.empty_like(self.psi[0])
+            gqc = torch.empty(2, dtype=torch.float64, device=self.device)
+        adjoint(self.ctx, n, dt, every, ckpt.data_ptr(), dl.data_ptr(), ws.data_ptr(), grad.data_ptr(), gqc.data_ptr())
+        self.stream.synchronize()
+        return grad, gqc
+
     def observables(self, group=0):
         """Per-sample (N, F_z, E) [S, 3] as a numpy array."""
         with self.torch.cuda.stream(self.stream):
@@ -333,3 +377,49 @@ class Sim:
         observables(self.ctx, group, out.data_ptr())
         with self.torch.cuda.stream(self.stream):
             return out.cpu().numpy()
+
+
+def _loss_from_bins(bins, target, mask):
+    sbar = bins.mean(0)
+    return ((sbar - target) ** 2 * mask).sum(), sbar
+
+
+def make_split_step_loss():
+    """torch.autograd.Function for L = sum_{k_b < k_cut} (S_b(t_T) - T_b)^2, S_b the
+    sample mean of the shell means of |DFT F_perp|^2 / N_sites after `steps` steps
+    from psi0; differentiable in psi0 (complex), q and c1 through the library's
+    reverse mode (checkpoints every `every` steps)."""
+    import torch
+
+    class SplitStepLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, psi0, q, c1, target, k_cut, steps, dt, every, grid, c0=1.0, dtype="c64"):
+            params = make_params(c0, float(c1), float(q))
+            sim = Sim([grid], params, dtype=dtype, device=psi0.device)
+            sim.set_fields([psi0.detach()])
+            ckpt = sim.forward_ckpt(steps, dt, every)
+            bins = sim.structure_factor_device()
+            with torch.cuda.stream(sim.stream):
+                g = sim.grids[0]
+                nmax = max(g.n[a] for a in range(g.dim))
+                kb = torch.arange(bins.shape[1], dtype=torch.float64, device=bins.device) * 2 * math.pi / (nmax * g.dx)
+                mask = (kb < k_cut).to(torch.float64)
+                tgt = torch.as_tensor(target, dtype=torch.float64).to(bins.device)
+                L, sbar = _loss_from_bins(bins, tgt, mask)
+                L = L.detach()
+            sim.stream.synchronize()
+            fctx.sim, fctx.ckpt, fctx.steps, fctx.dt, fctx.every = sim, ckpt, steps, dt, every
+            fctx.psi_dtype = psi0.dtype
+            fctx.dl = (2.0 * (sbar - tgt) * mask / bins.shape[0]).expand_as(bins).contiguous()
+            return L.to(psi0.device)
+
+        @staticmethod
+        def backward(fctx, gl):
+            sim = fctx.sim
+            grad, gqc = sim.adjoint(fctx.steps, fctx.dt, fctx.every, fctx.ckpt, fctx.dl)
+            gl = gl.to(torch.float64)
+            gpsi = grad.to(fctx.psi_dtype) * gl.to(fctx.psi_dtype)
+            sim.close()
+            return (gpsi, gqc[0] * gl, gqc[1] * gl) + (None,) * 8
+
+    return SplitStepLoss

@@ -1,0 +1,147 @@
+"""Reverse mode on the GPU: gradients of a structure-factor loss against the
+differentiable FP64 oracle (torch autograd) and against central differences."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import autodiff as A
+from oracle import spin1 as O
+from tests.inputs import random_field, uniform_unit
+
+pytestmark = pytest.mark.gpu
+
+C0, C1, Q = 1.0, -0.3, 0.09
+
+
+def loss_weights(bins, target, mask):
+    s = bins.shape[0]
+    sbar = bins.mean(0)
+    L = float(np.sum((sbar - target) ** 2 * mask))
+    dl = np.tile(2.0 * (sbar - target) * mask / s, (s, 1))
+    return L, dl
+
+
+def gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every, dtype="c128", q=Q, c1=C1):
+    sim = lib.Sim([grid], dict(c0=C0, c1=c1, q=q), dtype=dtype)
+    sim.set_fields([psi0])
+    ckpt = sim.forward_ckpt(nsteps, dt, every)
+    bins = sim.structure_factor_samples()
+    g = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    mask = O.bin_k(g) < k_cut
+    L, dl = loss_weights(bins, target, mask)
+    grad, gqc = sim.adjoint(nsteps, dt, every, ckpt, dl)
+    out = (L, grad.cpu().numpy().astype(np.complex128), float(gqc[0]), float(gqc[1]))
+    sim.close()
+    return out
+
+
+def gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q, c1=C1, dtype="c128"):
+    sim = lib.Sim([grid], dict(c0=C0, c1=c1, q=q), dtype=dtype)
+    sim.set_fields([psi0])
+    sim.step(nsteps, dt)
+    bins = sim.structure_factor_samples()
+    g = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    sim.close()
+    return loss_weights(bins, target, O.bin_k(g) < k_cut)[0]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("grid,nsteps,every,dt", [
+    ((2, (16, 8), 0.5, 2), 6, 4, 0.05),
+    ((1, (64,), 0.5, 2), 10, 3, 0.05),
+    ((3, (16, 8, 8), 0.5, 1), 3, 2, 0.05),
+    ((2, (32, 32), 0.5, 2), 50, 7, 0.02),
+])
+def test_adjoint_matches_oracle_gradient(lib, grid, nsteps, every, dt):
+    g = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(40 + nsteps, g.shape, noise=0.4)
+    nb = O.num_bins(g)
+    target = 8.0 * (1.0 + 0.1 * uniform_unit(41, (nb,)))
+    k_cut = 3.0
+    Lr, gr, gqr, gcr = A.gradients(psi0, Q, C1, C0, target, k_cut, nsteps, dt, g)
+    L, gp, gq, gc = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every)
+    assert abs(L - Lr) <= 1e-10 * abs(Lr)
+    assert rel(gp, gr) < 1e-10
+    assert abs(gq - gqr) <= 1e-10 * max(abs(gqr), 1e-3)
+    assert abs(gc - gcr) <= 1e-10 * max(abs(gcr), 1e-3)
+
+
+def test_adjoint_central_differences(lib):
+    """dL/dq, dL/dc1 and dL/dpsi0 along seeded directions against central
+    differences of the FP64 GPU forward map (h = 1e-4)."""
+    grid = (2, (64, 64), 0.5, 4)
+    g = O.Grid(2, (64, 64), 0.5, 4)
+    psi0 = O.init_wigner(1005, g, O.Params(C0, C1, Q))
+    nsteps, dt, every, k_cut = 100, 0.02, 10, 1.0
+    nb = O.num_bins(g)
+    s0 = 4 * (0.5 / g.cell) * (1 + 0.5 / g.cell)
+    target = s0 * (1.0 + 0.1 * uniform_unit(42, (nb,)))
+    L, gp, gq, gc = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every)
+    h = 1e-4
+    fq = (gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q + h)
+          - gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q - h)) / (2 * h)
+    fc = (gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, c1=C1 + h)
+          - gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, c1=C1 - h)) / (2 * h)
+    assert abs(gq - fq) <= 1e-5 * abs(fq)
+    assert abs(gc - fc) <= 1e-5 * abs(fc)
+    rng = np.random.default_rng(43)
+    for _ in range(3):
+        v = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
+        v /= np.linalg.norm(v) / math.sqrt(v.size)
+        fd = (gpu_loss(lib, grid, psi0 + h * v, target, k_cut, nsteps, dt)
+              - gpu_loss(lib, grid, psi0 - h * v, target, k_cut, nsteps, dt)) / (2 * h)
+        an = float(np.sum(np.real(np.conj(gp) * v)))
+        assert abs(an - fd) <= 1e-5 * abs(fd)
+
+
+def test_split_step_loss_autograd(lib):
+    """The torch.autograd.Function wrapper reproduces the oracle's loss and gradients."""
+    grid = (2, (16, 16), 0.5, 2)
+    g = O.Grid(2, (16, 16), 0.5, 2)
+    psi0 = random_field(44, g.shape, noise=0.4)
+    nb = O.num_bins(g)
+    target = 8.0 * (1.0 + 0.1 * uniform_unit(45, (nb,)))
+    Lr, gr, gqr, gcr = A.gradients(psi0, Q, C1, C0, target, 3.0, 8, 0.05, g)
+    Loss = lib.make_split_step_loss()
+    p = torch.tensor(psi0, dtype=torch.complex128, device="cuda", requires_grad=True)
+    q = torch.tensor(Q, dtype=torch.float64, device="cuda", requires_grad=True)
+    c1 = torch.tensor(C1, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = Loss.apply(p, q, c1, target, 3.0, 8, 0.05, 3, grid, C0, "c128")
+    L.backward()
+    assert abs(float(L) - Lr) <= 1e-10 * abs(Lr)
+    assert rel(p.grad.cpu().numpy(), gr) < 1e-10
+    assert abs(float(q.grad) - gqr) <= 1e-10 * abs(gqr)
+    assert abs(float(c1.grad) - gcr) <= 1e-10 * abs(gcr)
+
+
+def test_single_precision_adjoint_close_to_double(lib):
+    grid = (2, (32, 32), 0.5, 2)
+    g = O.Grid(2, (32, 32), 0.5, 2)
+    psi0 = random_field(46, g.shape, noise=0.4)
+    nb = O.num_bins(g)
+    target = 8.0 * (1.0 + 0.1 * uniform_unit(47, (nb,)))
+    a = gpu_grad(lib, grid, psi0, target, 3.0, 20, 0.02, 5, dtype="c128")
+    b = gpu_grad(lib, grid, psi0, target, 3.0, 20, 0.02, 5, dtype="c64")
+    assert abs(b[0] - a[0]) <= 1e-5 * abs(a[0])
+    assert rel(b[1], a[1]) < 1e-4
+    assert abs(b[2] - a[2]) <= 1e-4 * abs(a[2])
+    assert abs(b[3] - a[3]) <= 1e-4 * abs(a[3])
+
+
+def test_adjoint_argument_errors(lib):
+    sim = lib.Sim([(1, (64,), 0.5, 1)], dict(c0=C0, c1=C1, q=Q), dtype="c128")
+    sim.init_wigner(1)
+    with pytest.raises(lib.Spin1Error):
+        sim.forward_ckpt(0, 0.01, 1)
+    with pytest.raises(lib.Spin1Error):
+        sim.forward_ckpt(4, 0.01, 0)
+    two = lib.Sim([(1, (64,), 0.5, 1), (1, (32,), 0.5, 1)], dict(c0=C0, c1=C1, q=Q), dtype="c128")
+    two.init_wigner(1)
+    with pytest.raises(lib.Spin1Error) as ei:
+        two.forward_ckpt(4, 0.01, 2)
+    assert ei.value.code == lib.EUNSUPPORTED
