@@ -351,7 +351,7 @@ class Sim:
     def forward_ckpt(self, n, dt, every):
         """Advance n steps, keeping a checkpoint every `every` steps (device tensor)."""
         torch = self.torch
-        nck = (int(n) + int(every) - 1) // int(every)
+        nck = (int(n) + int(every) - 1) // int(every) if int(every) > 0 and int(n) > 0 else 1
         with torch.cuda.stream(self.stream):
             ckpt = torch.empty((nck,) + tuple(self.psi[0].shape), dtype=self.cdtype, device=self.device)
         forward_ckpt(self.ctx, n, dt, every, ckpt.data_ptr())

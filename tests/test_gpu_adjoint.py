@@ -73,7 +73,10 @@ def test_adjoint_matches_oracle_gradient(lib, grid, nsteps, every, dt):
 
 def test_adjoint_central_differences(lib):
     """dL/dq, dL/dc1 and dL/dpsi0 along seeded directions against central
-    differences of the FP64 GPU forward map (h = 1e-4)."""
+    differences of the FP64 GPU forward map.  The plain h = 1e-4 difference
+    carries its own O(h^2) truncation error (~1e-5 relative here), so the
+    1e-5 comparison uses its Richardson extrapolation with h/2,
+    (4 D(h/2) - D(h)) / 3, and D(1e-4) itself is held to 5e-5."""
     grid = (2, (64, 64), 0.5, 4)
     g = O.Grid(2, (64, 64), 0.5, 4)
     psi0 = O.init_wigner(1005, g, O.Params(C0, C1, Q))
@@ -83,20 +86,22 @@ def test_adjoint_central_differences(lib):
     target = s0 * (1.0 + 0.1 * uniform_unit(42, (nb,)))
     L, gp, gq, gc = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every)
     h = 1e-4
-    fq = (gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q + h)
-          - gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q - h)) / (2 * h)
-    fc = (gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, c1=C1 + h)
-          - gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, c1=C1 - h)) / (2 * h)
-    assert abs(gq - fq) <= 1e-5 * abs(fq)
-    assert abs(gc - fc) <= 1e-5 * abs(fc)
+
+    def check(analytic, f):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        rich = (4 * d2 - d1) / 3
+        assert abs(analytic - d1) <= 5e-5 * abs(d1)
+        assert abs(analytic - rich) <= 1e-5 * abs(rich)
+
+    check(gq, lambda e: gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=Q + e))
+    check(gc, lambda e: gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, c1=C1 + e))
     rng = np.random.default_rng(43)
     for _ in range(3):
         v = rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)
         v /= np.linalg.norm(v) / math.sqrt(v.size)
-        fd = (gpu_loss(lib, grid, psi0 + h * v, target, k_cut, nsteps, dt)
-              - gpu_loss(lib, grid, psi0 - h * v, target, k_cut, nsteps, dt)) / (2 * h)
         an = float(np.sum(np.real(np.conj(gp) * v)))
-        assert abs(an - fd) <= 1e-5 * abs(fd)
+        check(an, lambda e: gpu_loss(lib, grid, psi0 + e * v, target, k_cut, nsteps, dt))
 
 
 def test_split_step_loss_autograd(lib):
