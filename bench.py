@@ -97,6 +97,52 @@ def fp32_vs_fp64_error():
     return err
 
 
+ADJOINT = dict(n=(256, 256), samples=16, steps=500, dt=0.02, every=23, k_cut=1.0,
+               params=dict(c0=1.0, c1=-0.1, q=0.09, n0=1.0, wigner_var=0.5), seed=1005)
+
+
+def adjoint_timing():
+    """Reverse mode on the 2D 256 x 256, 16-sample, 500-step workload
+    (complex64, checkpoints every 23 steps): forward + backward time over the
+    plain forward time."""
+    import numpy as np
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    a = ADJOINT
+    grid = (2, a["n"], 0.5, a["samples"])
+    sim = spin1.Sim([grid], a["params"], dtype="c64")
+    sim.init_wigner(a["seed"])
+    psi0 = sim.psi[0].clone()
+    sim.step(a["steps"], a["dt"])  # warm up (graphs, tables)
+    sim.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    sim.set_fields([psi0])
+    ev[0].record(sim.stream)
+    sim.step(a["steps"], a["dt"])
+    sim.structure_factor_device()
+    ev[1].record(sim.stream)
+    sim.set_fields([psi0])
+    ev[2].record(sim.stream)
+    ckpt = sim.forward_ckpt(a["steps"], a["dt"], a["every"])
+    bins = sim.structure_factor_samples()
+    nb = bins.shape[1]
+    kb = np.arange(nb) * 2 * np.pi / (a["n"][0] * 0.5)
+    target = bins.mean(0) * 1.05
+    dl = np.tile(2 * (bins.mean(0) - target) * (kb < a["k_cut"]) / bins.shape[0], (bins.shape[0], 1))
+    grad, gqc = sim.adjoint(a["steps"], a["dt"], a["every"], ckpt, dl)
+    ev[3].record(sim.stream)
+    sim.synchronize()
+    fwd = ev[0].elapsed_time(ev[1])
+    tot = ev[2].elapsed_time(ev[3])
+    sim.close()
+    del ckpt, grad
+    torch.cuda.empty_cache()
+    return {"workload": "2D 256x256, 16 samples, 500 steps, complex64, checkpoints every 23",
+            "forward_ms": fwd, "forward_backward_ms": tot, "ratio": tot / fwd,
+            "dL_dq": float(gqc[0]), "dL_dc1": float(gqc[1])}
+
+
 def oracle_baseline(budget_s=20.0):
     """The FP64 oracle on the host: one sample of the 512 x 512 workload,
     split steps until about budget_s seconds have passed."""
@@ -119,6 +165,54 @@ def oracle_baseline(budget_s=20.0):
     return g.sites * nsteps / el, nsteps, el
 
 
+def profile_pass():
+    """Short run for hardware-counter passes: a few split steps of the 2D
+    workload, then a plain device copy of 402.65 MB (read and written once) as
+    the calibration kernel of known traffic."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    w = WORKLOAD
+    sim = spin1.Sim([(w["dim"], w["n"], w["dx"], w["samples"])], w["params"], dtype="c64")
+    sim.init_wigner(w["seed"])
+    sim.set_option(spin1.OPT_GRAPHS, 0)
+    sim.step(3, w["dt"])
+    sim.synchronize()
+    sim.close()
+    n = 64 * 512 * 512 * 3  # complex64 values of one field: 402.65 MB
+    src = torch.ones(n, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("profile pass done: copy of %d bytes" % (n * 8), flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_math.hpp"):
+        with open(os.path.join(ROOT, "paper_2310_03636_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_xpass_ypass_2d512_s64.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("traffic:"):
+            parts = dict(kv.split("=") for kv in line.split()[1:])
+            rec[parts["kind"]] = parts
+    r = rec.get(kernel)
+    if not r or r.get("source") != kernel_source_hash():
+        return None
+    return float(r["bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,7 +221,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for rocprofv3 counter passes (no JSON line)")
     args = ap.parse_args()
+    if args.profile_pass:
+        profile_pass()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the Wigner samples are independent, so N GPUs would each run "
               "this same single-GPU workload on their own share (see DESIGN.md); --gpus %d is not run."
@@ -172,6 +271,7 @@ def main():
     torch.cuda.empty_cache()
 
     err = fp32_vs_fp64_error()
+    adj = adjoint_timing()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -198,7 +298,7 @@ def main():
                    "grid": list(w["n"]), "samples": w["samples"], "split_steps_per_step": w["split_steps"],
                    "dt": w["dt"], "params": w["params"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": measured_traffic(dom),
                      "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes},
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
         "hbm_algorithmic_GBps_whole_step": None,
@@ -206,6 +306,7 @@ def main():
         "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
                  "ms_per_step": ev64 / args.fp64_steps},
         "speedup_fp32_vs_fp64": value / value64,
+        "adjoint": adj,
         "err_fp32_vs_fp64_rel_l2_100_split_steps": err,
         "wall_s": wall,
         "cpu_baseline": cpu,

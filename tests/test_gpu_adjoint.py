@@ -150,3 +150,32 @@ def test_adjoint_argument_errors(lib):
     with pytest.raises(lib.Spin1Error) as ei:
         two.forward_ckpt(4, 0.01, 2)
     assert ei.value.code == lib.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("nsteps,h", [(100, 1e-5), (250, 1e-6)])
+def test_adjoint_full_grid_central_differences(lib, nsteps, h):
+    """The 2D 256x256, 16-sample workload with checkpoints every 23 steps:
+    dL/dq and dL/dc1 of the FP64 path against Richardson-extrapolated central
+    differences.  The loss of these chaotic runs grows ever more sensitive with
+    the horizon (dL/dq ~ 1e3 at 100 steps, ~1e4 at 250, ~3e7 at 500 steps), so
+    the difference step must shrink with it to stay in the linear regime; at
+    500 steps no FP64 difference quotient resolves the derivative to 1e-5
+    (roundoff of the loss, amplified by the same chaos, sets in first), and
+    that horizon is covered by the oracle-gradient comparison instead."""
+    grid = (2, (256, 256), 0.5, 16)
+    g = O.Grid(2, (256, 256), 0.5, 16)
+    dt, every, k_cut = 0.02, 23, 1.0
+    sim = lib.Sim([grid], dict(c0=C0, c1=-0.1, q=0.09), dtype="c128")
+    sim.init_wigner(1005)
+    psi0 = sim.fields()[0]
+    sim.close()
+    nb = O.num_bins(g)
+    s0 = 4 * (0.5 / g.cell) * (1 + 0.5 / g.cell)
+    target = s0 * (1.0 + 0.1 * uniform_unit(48, (nb,)))
+    L, gp, gq, gc = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every, q=0.09, c1=-0.1)
+    for analytic, f in ((gq, lambda e: gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=0.09 + e, c1=-0.1)),
+                        (gc, lambda e: gpu_loss(lib, grid, psi0, target, k_cut, nsteps, dt, q=0.09, c1=-0.1 + e))):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        rich = (4 * d2 - d1) / 3
+        assert abs(analytic - rich) <= 1e-5 * abs(rich), (analytic, d1, rich)
