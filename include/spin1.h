@@ -159,6 +159,20 @@ SPIN1_API int spin1_forward_ckpt(spin1_ctx* ctx, int64_t n, double dt, int64_t e
 SPIN1_API int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every, const void* ckpt_dev,
                             const double* dL_dbins_dev, void* adj_ws_dev, void* grad_psi0_dev, double* grad_qc1_dev);
 
+/* Autotuning of the step passes.  Each step pass (pass 0: the x-pass,
+ * pass 1: the strided y/z pass) is compiled in spin1_num_variants() variants
+ * per axis length n (workgroup shape, columns per tile, radix).
+ * spin1_autotune copies each bound field into scratch_dev (at least the
+ * largest field; the bound fields are not touched), times every variant of
+ * every pass the bound groups use (reps launches each, HIP events on the
+ * context's stream; synchronises) and keeps the fastest per (pass, n, dtype)
+ * for this context.  spin1_get_variant / spin1_set_variant read and restore
+ * the choices (e.g. from a cache file). */
+SPIN1_API int32_t spin1_num_variants(void);
+SPIN1_API int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t reps);
+SPIN1_API int spin1_get_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t* variant);
+SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t variant);
+
 /* Options (spin1_set_option).
  * SPIN1_OPT_GRAPHS: 1 (default) = spin1_step captures the launches of an
  *   n-step call into a HIP graph on first use and replays it for later calls

@@ -217,6 +217,8 @@ struct spin1_ctx {
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
+  // step-pass variants chosen by the autotuner: [pass 0 = x, 1 = strided][double][log2 N]
+  int8_t variant[2][2][13] = {};
   void drop_graphs() {
     for (GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
@@ -348,6 +350,14 @@ SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int6
 // opening half into R(dt); the last step closes with R(dt/2) (x-pass epilogue
 // in 1D, k_local otherwise).  tau_open = tau_close = 0 gives the kinetic +
 // Zeeman passes alone, which the reverse sweep applies to the adjoint field.
+int log2_of(int n) {
+  int r = 0;
+  while ((1 << (r + 1)) <= n) ++r;
+  return r;
+}
+
+int variant_of(spin1_ctx* ctx, int pass, int n) { return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)]; }
+
 int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double dt, double tau_open,
                        double tau_close) {
   XPassArgs xa = xargs(ctx, G);
@@ -357,14 +367,14 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
   hipError_t e;
   {
     Prof pr(ctx, SPIN1_K_XPASS);
-    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa);
+    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, variant_of(ctx, 0, G.geo.n[0]));
   }
   if (e != hipSuccess) return hip_fail(e, "x-pass");
   for (int a = 1; a < G.geo.dim; ++a) {
     const SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
     {
       Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
-      e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa);
+      e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa, variant_of(ctx, 1, G.geo.n[a]));
     }
     if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
   }
@@ -787,6 +797,111 @@ int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every, const voi
     return hip_fail(e, "gradient output");
   if ((e = hipMemcpyAsync(grad_qc1_dev, acc, 2 * sizeof(double), hipMemcpyDeviceToDevice, st)) != hipSuccess)
     return hip_fail(e, "gradient output");
+  return SPIN1_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the step passes
+// ---------------------------------------------------------------------------
+int32_t spin1_num_variants(void) { return step_variants(); }
+
+static int check_variant_args(spin1_ctx* ctx, int32_t pass, int32_t n) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  if (pass != 0 && pass != 1) return fail(SPIN1_EINVAL, "pass must be 0 (x) or 1 (strided)");
+  if (!is_pow2(n) || n < 8 || n > (pass == 0 ? 4096 : 1024)) return fail(SPIN1_EINVAL, "no kernel for n = %d", n);
+  return SPIN1_OK;
+}
+
+int spin1_get_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t* variant) {
+  int rc = check_variant_args(ctx, pass, n);
+  if (rc) return rc;
+  if (!variant) return fail(SPIN1_EINVAL, "variant pointer is NULL");
+  *variant = variant_of(ctx, pass, n);
+  return SPIN1_OK;
+}
+
+int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t variant) {
+  int rc = check_variant_args(ctx, pass, n);
+  if (rc) return rc;
+  if (variant < 0 || variant >= step_variants()) return fail(SPIN1_EINVAL, "variant %d out of range", variant);
+  ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)] = int8_t(variant);
+  ctx->version++;
+  return SPIN1_OK;
+}
+
+int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t reps) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!scratch_dev) return fail(SPIN1_EINVAL, "scratch pointer is NULL");
+  if (reps < 1 || reps > 1000) return fail(SPIN1_EINVAL, "reps must be in 1..1000");
+  const double dt = ctx->tab_dt != 0.0 ? ctx->tab_dt : 0.01;
+  if (!ctx->tab_valid || ctx->tab_dt != dt || ctx->tab_q != ctx->p.q)
+    if ((rc = make_tables(ctx, dt))) return rc;
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return fail(SPIN1_EHIP, "hipEventCreate");
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(SPIN1_EHIP, "hipEventCreate");
+  }
+  double total[2][13][8] = {};
+  bool seen[2][13] = {};
+  const int nv = step_variants();
+  rc = SPIN1_OK;
+  for (auto& G : ctx->groups) {
+    const size_t fb = size_t(G.geo.S) * 3 * size_t(G.geo.sites) * (ctx->dbl ? 16 : 8);
+    if (fb > scratch_bytes) {
+      rc = fail(SPIN1_EINVAL, "scratch of %zu bytes is smaller than a field (%zu bytes)", scratch_bytes, fb);
+      break;
+    }
+    hipError_t e = hipMemcpyAsync(scratch_dev, G.psi, fb, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "autotune copy");
+      break;
+    }
+    for (int axis = 0; axis < G.geo.dim && !rc; ++axis) {
+      const int pass = axis == 0 ? 0 : 1;
+      const int lg = log2_of(G.geo.n[axis]);
+      seen[pass][lg] = true;
+      for (int v = 0; v < nv && !rc; ++v) {
+        auto launch = [&]() {
+          if (pass == 0) {
+            XPassArgs xa = xargs(ctx, G);
+            xa.psi = scratch_dev;
+            xa.tau_pre = dt;
+            return launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, v);
+          }
+          const SPassArgs sa = sargs(ctx, G, axis, scratch_dev, int64_t(3) * G.geo.S);
+          return launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[axis], sa, v);
+        };
+        e = launch();  // warm-up (also loads the code object)
+        if (e == hipSuccess) e = hipEventRecord(ev[0], ctx->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) {
+          rc = hip_fail(e, "autotune timing");
+          break;
+        }
+        total[pass][lg][v] += double(ms);
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (rc) return rc;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int lg = 0; lg < 13; ++lg) {
+      if (!seen[pass][lg]) continue;
+      int best = 0;
+      for (int v = 1; v < nv; ++v)
+        if (total[pass][lg][v] < total[pass][lg][best]) best = v;
+      ctx->variant[pass][ctx->dbl ? 1 : 0][lg] = int8_t(best);
+    }
+  ctx->version++;
   return SPIN1_OK;
 }
 

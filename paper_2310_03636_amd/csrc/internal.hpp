@@ -60,8 +60,10 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
                          double dx);
 hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
                        double n0, double wigner_var);
-hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a);
-hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a);
+// variant: step-pass variant index (0 = default), ignored by the other modes
+hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant = 0);
+hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant = 0);
+int step_variants();
 hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
 hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
                       const int32_t* offs, int nbins, double* out);

@@ -22,30 +22,40 @@ namespace spin1 {
 // launch configurations
 // --------------------------------------------------------------------------
 // x-pass: radix R, N/R threads per pencil, P pencils per workgroup; STREAM
-// selects the persistent prefetching kernel for the step pass.
-template <int N, typename Real>
+// selects the persistent prefetching kernel for the step pass.  V picks one of
+// the step-pass variants the autotuner times: workgroups of about 256 (V = 0),
+// 128 (V = 1) or 512 (V = 2) threads.
+template <int N, typename Real, int V = 0>
 struct XCfg {
   // radix 16 only where 3 x 16 single-precision values per thread still fit
   static constexpr int R = N <= 8 ? N : ((N <= 1024 || sizeof(Real) == 8) ? 8 : 16);
   static constexpr int T = N / R;
-  static constexpr int P = T >= 256 ? 1 : 256 / T;
+  static constexpr int TARGET = V == 1 ? 128 : (V == 2 ? 512 : 256);
+  static constexpr int P = T >= TARGET ? 1 : TARGET / T;
   static constexpr int THREADS = T * P;
   // the streaming kernel keeps twiddles and two phase tables in LDS
   static constexpr int STREAM_LDS = P * (N + N / 16) * int(sizeof(Cx<Real>)) + 3 * N * 16;
   static constexpr bool STREAM = STREAM_LDS <= 96 * 1024;
 };
 
-// strided pass: radix R, TX adjacent columns per workgroup (TX x N/R threads)
-template <int N, typename Real>
+// strided pass: radix R, TX adjacent columns per workgroup (TX x N/R threads).
+// Step-pass variants: V = 0 the default, V = 1 half the columns, V = 2 radix 8.
+template <int N, typename Real, int V = 0>
 struct SCfg {
-  static constexpr int R = N <= 8 ? N : (N <= 128 ? 8 : 16);
+  static constexpr int R0 = N <= 8 ? N : (N <= 128 ? 8 : 16);
+  static constexpr int R = (V == 2 && N >= 64) ? 8 : R0;
   static constexpr int T = N / R;
   static constexpr int CB = int(sizeof(Cx<Real>));
   static constexpr int TXRAW = 65536 / (N * CB);
-  static constexpr int TX = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
+  static constexpr int TX0 = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
+  static constexpr int TX1 = (V == 1 && TX0 > 4) ? TX0 / 2 : TX0;
+  // keep workgroups within 1024 threads
+  static constexpr int TX = TX1 * T > 1024 ? 1024 / T : TX1;
   static constexpr int THREADS = TX * T;
   static constexpr bool STREAM = true;
 };
+
+constexpr int kStepVariants = 3;
 
 int xpass_pencils(int n, bool dbl) {
   switch (n) {
@@ -350,10 +360,10 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
 // prefetch had arrived (the vector-memory counter retires in order).
-template <typename Real, int N>
-__global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
+template <typename Real, int N, int V>
+__global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
-  constexpr int R = SCfg<N, Real>::R, T = SCfg<N, Real>::T, TX = SCfg<N, Real>::TX;
+  constexpr int R = SCfg<N, Real, V>::R, T = SCfg<N, Real, V>::T, TX = SCfg<N, Real, V>::TX;
   __shared__ C lds[N * (TX + 1)];
   __shared__ TabEntry<Real> tw[N];
   __shared__ TabEntry<Real> ph[N];
@@ -405,11 +415,11 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass_stream(SPass
   }
 }
 
-template <typename Real, int N, bool ENABLED = XCfg<N, Real>::STREAM>
-__global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
+template <typename Real, int N, int V, bool ENABLED = XCfg<N, Real, V>::STREAM>
+__global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
  if constexpr (ENABLED) {
   using C = Cx<Real>;
-  constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
+  constexpr int R = XCfg<N, Real, V>::R, T = XCfg<N, Real, V>::T, P = XCfg<N, Real, V>::P;
   __shared__ C lds[P * RowPad<N, T>::ROW];
   __shared__ TabEntry<Real> stw[N];
   // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
@@ -816,102 +826,125 @@ static int64_t stream_grid(K kernel, int threads, int64_t items) {
   return items < g ? items : g;
 }
 
-template <typename Real, int N, int MODE>
-static hipError_t xpass_n(hipStream_t st, const XPassArgs& a) {
-  constexpr int P = XCfg<N, Real>::P;
-  const int64_t pencils = int64_t(a.S) * a.rows;
-  const int64_t blocks = (pencils + P - 1) / P;
-  if constexpr (MODE == MODE_STEP && XCfg<N, Real>::STREAM) {
-    XPassArgs b = a;
-    b.lg_rows = ilog2(a.rows);
-    const int64_t grid = stream_grid(k_xpass_stream<Real, N>, XCfg<N, Real>::THREADS, blocks);
-    hipLaunchKernelGGL((k_xpass_stream<Real, N>), dim3(unsigned(grid)), dim3(XCfg<N, Real>::THREADS), 0, st, b,
-                       blocks);
-  } else {
-    hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
-  }
+template <typename Real, int N, int V>
+static hipError_t xpass_stream_v(hipStream_t st, const XPassArgs& a) {
+  constexpr int P = XCfg<N, Real, V>::P;
+  const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
+  XPassArgs b = a;
+  b.lg_rows = ilog2(a.rows);
+  const int64_t grid = stream_grid(k_xpass_stream<Real, N, V>, XCfg<N, Real, V>::THREADS, blocks);
+  hipLaunchKernelGGL((k_xpass_stream<Real, N, V>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS), 0, st, b,
+                     blocks);
   return hipGetLastError();
 }
 
+template <typename Real, int N, int MODE>
+static hipError_t xpass_n(hipStream_t st, const XPassArgs& a, int variant) {
+  if constexpr (MODE == MODE_STEP && XCfg<N, Real>::STREAM) {
+    // variants whose tables no longer fit in LDS fall back to the default one
+    if (variant == 1 && XCfg<N, Real, 1>::STREAM) return xpass_stream_v<Real, N, 1>(st, a);
+    if (variant == 2 && XCfg<N, Real, 2>::STREAM) return xpass_stream_v<Real, N, 2>(st, a);
+    return xpass_stream_v<Real, N, 0>(st, a);
+  } else {
+    constexpr int P = XCfg<N, Real>::P;
+    const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
+    hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+}
+
 template <typename Real, int MODE>
-static hipError_t xpass_mode(hipStream_t st, int n, const XPassArgs& a) {
+static hipError_t xpass_mode(hipStream_t st, int n, const XPassArgs& a, int v) {
   switch (n) {
-    case 8: return xpass_n<Real, 8, MODE>(st, a);
-    case 16: return xpass_n<Real, 16, MODE>(st, a);
-    case 32: return xpass_n<Real, 32, MODE>(st, a);
-    case 64: return xpass_n<Real, 64, MODE>(st, a);
-    case 128: return xpass_n<Real, 128, MODE>(st, a);
-    case 256: return xpass_n<Real, 256, MODE>(st, a);
-    case 512: return xpass_n<Real, 512, MODE>(st, a);
-    case 1024: return xpass_n<Real, 1024, MODE>(st, a);
-    case 2048: return xpass_n<Real, 2048, MODE>(st, a);
-    case 4096: return xpass_n<Real, 4096, MODE>(st, a);
+    case 8: return xpass_n<Real, 8, MODE>(st, a, v);
+    case 16: return xpass_n<Real, 16, MODE>(st, a, v);
+    case 32: return xpass_n<Real, 32, MODE>(st, a, v);
+    case 64: return xpass_n<Real, 64, MODE>(st, a, v);
+    case 128: return xpass_n<Real, 128, MODE>(st, a, v);
+    case 256: return xpass_n<Real, 256, MODE>(st, a, v);
+    case 512: return xpass_n<Real, 512, MODE>(st, a, v);
+    case 1024: return xpass_n<Real, 1024, MODE>(st, a, v);
+    case 2048: return xpass_n<Real, 2048, MODE>(st, a, v);
+    case 4096: return xpass_n<Real, 4096, MODE>(st, a, v);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename Real>
-static hipError_t xpass_t(hipStream_t st, int mode, int n, const XPassArgs& a) {
+static hipError_t xpass_t(hipStream_t st, int mode, int n, const XPassArgs& a, int v) {
   switch (mode) {
-    case MODE_STEP: return xpass_mode<Real, MODE_STEP>(st, n, a);
-    case MODE_MEASURE: return xpass_mode<Real, MODE_MEASURE>(st, n, a);
-    case MODE_SF: return xpass_mode<Real, MODE_SF>(st, n, a);
-    case MODE_SF_POWER: return xpass_mode<Real, MODE_SF_POWER>(st, n, a);
+    case MODE_STEP: return xpass_mode<Real, MODE_STEP>(st, n, a, v);
+    case MODE_MEASURE: return xpass_mode<Real, MODE_MEASURE>(st, n, a, v);
+    case MODE_SF: return xpass_mode<Real, MODE_SF>(st, n, a, v);
+    case MODE_SF_POWER: return xpass_mode<Real, MODE_SF_POWER>(st, n, a, v);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a) {
-  return dbl ? xpass_t<double>(st, mode, n, a) : xpass_t<float>(st, mode, n, a);
+hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant) {
+  return dbl ? xpass_t<double>(st, mode, n, a, variant) : xpass_t<float>(st, mode, n, a, variant);
 }
 
-template <typename Real, int N, int MODE>
-static hipError_t spass_n(hipStream_t st, const SPassArgs& a) {
-  constexpr int TX = SCfg<N, Real>::TX;
+template <typename Real, int N, int V>
+static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
+  constexpr int TX = SCfg<N, Real, V>::TX;
   if (a.inner % TX != 0) return hipErrorInvalidValue;
   const int64_t blocks = a.nfield * a.outer * (a.inner / TX);
-  if constexpr (MODE == MODE_STEP && SCfg<N, Real>::STREAM) {
-    SPassArgs b = a;
-    b.lg_tiles = ilog2(a.inner / TX);
-    b.lg_outer = ilog2(a.outer);
-    const int64_t grid = stream_grid(k_spass_stream<Real, N>, SCfg<N, Real>::THREADS, blocks);
-    hipLaunchKernelGGL((k_spass_stream<Real, N>), dim3(unsigned(grid)), dim3(SCfg<N, Real>::THREADS), 0, st, b,
-                       blocks);
-  } else {
-    hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
-  }
+  SPassArgs b = a;
+  b.lg_tiles = ilog2(a.inner / TX);
+  b.lg_outer = ilog2(a.outer);
+  const int64_t grid = stream_grid(k_spass_stream<Real, N, V>, SCfg<N, Real, V>::THREADS, blocks);
+  hipLaunchKernelGGL((k_spass_stream<Real, N, V>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0, st, b,
+                     blocks);
   return hipGetLastError();
 }
 
+template <typename Real, int N, int MODE>
+static hipError_t spass_n(hipStream_t st, const SPassArgs& a, int variant) {
+  if constexpr (MODE == MODE_STEP && SCfg<N, Real>::STREAM) {
+    if (variant == 1) return spass_stream_v<Real, N, 1>(st, a);
+    if (variant == 2) return spass_stream_v<Real, N, 2>(st, a);
+    return spass_stream_v<Real, N, 0>(st, a);
+  } else {
+    constexpr int TX = SCfg<N, Real>::TX;
+    if (a.inner % TX != 0) return hipErrorInvalidValue;
+    const int64_t blocks = a.nfield * a.outer * (a.inner / TX);
+    hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
+    return hipGetLastError();
+  }
+}
+
 template <typename Real, int MODE>
-static hipError_t spass_mode(hipStream_t st, int n, const SPassArgs& a) {
+static hipError_t spass_mode(hipStream_t st, int n, const SPassArgs& a, int v) {
   switch (n) {
-    case 8: return spass_n<Real, 8, MODE>(st, a);
-    case 16: return spass_n<Real, 16, MODE>(st, a);
-    case 32: return spass_n<Real, 32, MODE>(st, a);
-    case 64: return spass_n<Real, 64, MODE>(st, a);
-    case 128: return spass_n<Real, 128, MODE>(st, a);
-    case 256: return spass_n<Real, 256, MODE>(st, a);
-    case 512: return spass_n<Real, 512, MODE>(st, a);
-    case 1024: return spass_n<Real, 1024, MODE>(st, a);
+    case 8: return spass_n<Real, 8, MODE>(st, a, v);
+    case 16: return spass_n<Real, 16, MODE>(st, a, v);
+    case 32: return spass_n<Real, 32, MODE>(st, a, v);
+    case 64: return spass_n<Real, 64, MODE>(st, a, v);
+    case 128: return spass_n<Real, 128, MODE>(st, a, v);
+    case 256: return spass_n<Real, 256, MODE>(st, a, v);
+    case 512: return spass_n<Real, 512, MODE>(st, a, v);
+    case 1024: return spass_n<Real, 1024, MODE>(st, a, v);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename Real>
-static hipError_t spass_t(hipStream_t st, int mode, int n, const SPassArgs& a) {
+static hipError_t spass_t(hipStream_t st, int mode, int n, const SPassArgs& a, int v) {
   switch (mode) {
-    case MODE_STEP: return spass_mode<Real, MODE_STEP>(st, n, a);
-    case MODE_MEASURE: return spass_mode<Real, MODE_MEASURE>(st, n, a);
-    case MODE_SF: return spass_mode<Real, MODE_SF>(st, n, a);
-    case MODE_SF_POWER: return spass_mode<Real, MODE_SF_POWER>(st, n, a);
+    case MODE_STEP: return spass_mode<Real, MODE_STEP>(st, n, a, v);
+    case MODE_MEASURE: return spass_mode<Real, MODE_MEASURE>(st, n, a, v);
+    case MODE_SF: return spass_mode<Real, MODE_SF>(st, n, a, v);
+    case MODE_SF_POWER: return spass_mode<Real, MODE_SF_POWER>(st, n, a, v);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a) {
-  return dbl ? spass_t<double>(st, mode, n, a) : spass_t<float>(st, mode, n, a);
+hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant) {
+  return dbl ? spass_t<double>(st, mode, n, a, variant) : spass_t<float>(st, mode, n, a, variant);
 }
+
+int step_variants() { return kStepVariants; }
 
 static unsigned grid_for(int64_t work, int threads) {
   int64_t b = (work + threads - 1) / threads;

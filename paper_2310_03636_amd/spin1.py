@@ -26,7 +26,7 @@ FUNCTIONS = [
     "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
     "spin1_observables", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
-    "spin1_last_error",
+    "spin1_num_variants", "spin1_autotune", "spin1_get_variant", "spin1_set_variant", "spin1_last_error",
 ]
 
 OPT_GRAPHS, OPT_GRAPH_MAX_STEPS = 0, 1
@@ -81,6 +81,10 @@ def load():
         "spin1_local_update": (ctypes.c_int, [vp, f64]),
         "spin1_set_option": (ctypes.c_int, [vp, i32, i64]),
         "spin1_adjoint_workspace_bytes": (sz, [gp, i32, i64]),
+        "spin1_num_variants": (i32, []),
+        "spin1_autotune": (ctypes.c_int, [vp, vp, sz, i32]),
+        "spin1_get_variant": (ctypes.c_int, [vp, i32, i32, ctypes.POINTER(i32)]),
+        "spin1_set_variant": (ctypes.c_int, [vp, i32, i32, i32]),
         "spin1_forward_ckpt": (ctypes.c_int, [vp, i64, f64, i64, vp]),
         "spin1_adjoint": (ctypes.c_int, [vp, i64, f64, i64, vp, vp, vp, vp, vp]),
         "spin1_profile_enable": (ctypes.c_int, [vp, i32]),
@@ -217,6 +221,24 @@ def profile_read(ctx):
     return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_KINDS)}
 
 
+def num_variants():
+    return int(load().spin1_num_variants())
+
+
+def autotune(ctx, scratch_ptr, scratch_bytes, reps=3):
+    _check(load().spin1_autotune(ctx, ctypes.c_void_p(int(scratch_ptr)), int(scratch_bytes), int(reps)))
+
+
+def get_variant(ctx, pass_, n):
+    v = ctypes.c_int32()
+    _check(load().spin1_get_variant(ctx, int(pass_), int(n), ctypes.byref(v)))
+    return int(v.value)
+
+
+def set_variant(ctx, pass_, n, variant):
+    _check(load().spin1_set_variant(ctx, int(pass_), int(n), int(variant)))
+
+
 def adjoint_workspace_bytes(grid, dtype, every):
     v = load().spin1_adjoint_workspace_bytes(ctypes.byref(grid), int(dtype), int(every))
     if v == 0:
@@ -346,6 +368,46 @@ class Sim:
         nmax = max(g.n[a] for a in range(g.dim))
         kb = np.arange(per.shape[1]) * 2.0 * math.pi / (nmax * g.dx)
         return kb, mean, se, bin_counts(g), per
+
+    # ---- autotuning ----
+    def pass_sizes(self):
+        """(pass, n) pairs of the step passes the bound groups use."""
+        out = set()
+        for g in self.grids:
+            out.add((0, g.n[0]))
+            for a in range(1, g.dim):
+                out.add((1, g.n[a]))
+        return sorted(out)
+
+    def autotune(self, reps=3, cache_path=None):
+        """Pick the fastest step-pass variants; with cache_path, reuse and
+        extend a JSON cache keyed by (arch, dtype, pass, n)."""
+        import json
+        import os
+
+        torch = self.torch
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        dname = "c64" if self.dtype_code == C64 else "c128"
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        keys = {(p, n): "%s/%s/%d/%d" % (arch, dname, p, n) for p, n in self.pass_sizes()}
+        if all(k in cache for k in keys.values()):
+            for (p, n), k in keys.items():
+                set_variant(self.ctx, p, n, cache[k])
+            return {k: cache[k] for k in keys.values()}
+        with torch.cuda.stream(self.stream):
+            nbytes = max(p.numel() * p.element_size() for p in self.psi)
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        autotune(self.ctx, scratch.data_ptr(), nbytes, reps)
+        self.stream.synchronize()
+        chosen = {k: get_variant(self.ctx, p, n) for (p, n), k in keys.items()}
+        if cache_path:
+            cache.update(chosen)
+            with open(cache_path, "w") as fh:
+                json.dump(cache, fh, indent=1, sort_keys=True)
+        return chosen
 
     # ---- reverse mode (one group) ----
     def forward_ckpt(self, n, dt, every):

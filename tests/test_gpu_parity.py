@@ -283,3 +283,52 @@ def test_graph_option_validation(lib):
         sim.set_option(lib.OPT_GRAPH_MAX_STEPS, 0)
     with pytest.raises(lib.Spin1Error):
         sim.set_option(99, 1)
+
+
+# ------------------------------------------------------------------ step-pass variants and autotuning
+@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 128), (512, 512), (256, 1024), (4096, 16)])
+def test_every_step_variant_matches_oracle(lib, nx, ny):
+    grid = (2, (nx, ny), 0.5, 2)
+    og = O.Grid(2, (nx, ny), 0.5, 2)
+    psi0 = random_field(nx + ny, og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(P1), og)
+    for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
+        for v in range(lib.num_variants()):
+            sim = lib.Sim([grid], P1, dtype=dtype)
+            lib.set_variant(sim.ctx, 0, nx, v)
+            lib.set_variant(sim.ctx, 1, ny, v)
+            sim.set_fields([psi0])
+            sim.step(1, 0.02)
+            assert rel(sim.fields()[0], ref) < tol, (dtype, v)
+            sim.close()
+
+
+def test_autotune_choices_and_cache(lib, tmp_path):
+    grids = [(2, (128, 64), 0.5, 4), (1, (1024,), 0.5, 8)]
+    sim = lib.Sim(grids, P1, dtype="c64")
+    sim.init_wigner(3)
+    before = sim.fields()
+    cache = tmp_path / "tune.json"
+    chosen = sim.autotune(reps=2, cache_path=str(cache))
+    assert set(chosen) and all(0 <= v < lib.num_variants() for v in chosen.values())
+    after = sim.fields()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)  # the bound fields are not touched
+    # a second object restores the same choices from the cache without timing
+    sim2 = lib.Sim(grids, P1, dtype="c64")
+    sim2.init_wigner(3)
+    again = sim2.autotune(cache_path=str(cache))
+    assert again == chosen
+    for (p, n) in sim2.pass_sizes():
+        key = [k for k in chosen if k.endswith("/%d/%d" % (p, n))][0]
+        assert lib.get_variant(sim2.ctx, p, n) == chosen[key]
+    # tuned stepping still matches the oracle
+    sim2.step(5, 0.02)
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        ref = O.evolve(O.init_wigner(3, og, oparams(P1), group=gi), 5, 0.02, oparams(P1), og)
+        assert rel(sim2.fields()[gi], ref) < 2e-5
+    with pytest.raises(lib.Spin1Error):
+        lib.set_variant(sim.ctx, 0, 512, 7)
+    with pytest.raises(lib.Spin1Error):
+        lib.set_variant(sim.ctx, 1, 4096, 0)
