@@ -143,6 +143,46 @@ def adjoint_timing():
             "dL_dq": float(gqc[0]), "dL_dc1": float(gqc[1])}
 
 
+OTHER_CONFIGS = {
+    "1d_256_s4_c128": dict(groups=[(1, (256,), 0.5, 4)], dtype="c128", dt=0.01, steps=1000,
+                           params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1001),
+    "3d_256_s8_c64": dict(groups=[(3, (256, 256, 256), 0.5, 8)], dtype="c64", dt=0.02, steps=20,
+                          params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003),
+    "uneven_c64": dict(groups=[(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
+                               (2, (1024, 1024), 0.5, 4)], dtype="c64", dt=0.02, steps=100,
+                       params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1004),
+}
+
+
+def other_configs():
+    """Site-steps/s of the other workloads (graph replay, autotuned passes)."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    out = {}
+    for name, c in OTHER_CONFIGS.items():
+        sim = spin1.Sim(c["groups"], c["params"], dtype=c["dtype"])
+        sim.init_wigner(c["seed"])
+        tuned = sim.autotune(reps=2)
+        sim.step(c["steps"], c["dt"])  # capture and warm up
+        sim.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(c["steps"], c["dt"])
+        e1.record(sim.stream)
+        sim.synchronize()
+        ms = e0.elapsed_time(e1)
+        sites = sum(g[3] * int(__import__("math").prod(g[1])) for g in c["groups"])
+        obs = sim.observables(0)
+        out[name] = {"value": sites * c["steps"] / (ms / 1e3), "unit": "site-steps/s", "steps": c["steps"],
+                     "ms_per_split_step": ms / c["steps"], "dtype": c["dtype"], "variants": tuned,
+                     "norm_sample0": float(obs[0, 0])}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def oracle_baseline(budget_s=20.0):
     """The FP64 oracle on the host: one sample of the 512 x 512 workload,
     split steps until about budget_s seconds have passed."""
@@ -272,6 +312,7 @@ def main():
 
     err = fp32_vs_fp64_error()
     adj = adjoint_timing()
+    others = other_configs()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -307,6 +348,7 @@ def main():
                  "ms_per_step": ev64 / args.fp64_steps},
         "speedup_fp32_vs_fp64": value / value64,
         "adjoint": adj,
+        "other_configs": others,
         "err_fp32_vs_fp64_rel_l2_100_split_steps": err,
         "wall_s": wall,
         "cpu_baseline": cpu,
