@@ -182,13 +182,19 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   used first out); spin1_bind and spin1_set_params retire them.
  * SPIN1_OPT_GRAPH_MAX_STEPS: longest step sequence in one graph (default
  *   1024); longer calls run as consecutive chunks, each ending at a
- *   synchronized time. */
-enum spin1_option { SPIN1_OPT_GRAPHS = 0, SPIN1_OPT_GRAPH_MAX_STEPS = 1 };
+ *   synchronized time.
+ * SPIN1_OPT_STEPS_PER_LAUNCH_1D: 1D groups run up to this many consecutive
+ *   split steps in one launch, each sample held on chip between steps
+ *   (default 64, range 1..1024); 1 = one x-pass launch per step, as for
+ *   2D/3D groups.  The result is the same map either way (same arithmetic,
+ *   different kernel). */
+enum spin1_option { SPIN1_OPT_GRAPHS = 0, SPIN1_OPT_GRAPH_MAX_STEPS = 1, SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 
 /* Kernel kinds reported by the profiling hooks. */
 enum spin1_kernel_kind {
-  SPIN1_K_XPASS = 0,       /* x-pass of a step (local update, FFT_x, phase, IFFT_x) */
+  SPIN1_K_XPASS = 0,       /* x-pass of a step (local update, FFT_x, phase, IFFT_x),
+                              or of several steps of a 1D group */
   SPIN1_K_YPASS = 1,       /* y-pass of a step */
   SPIN1_K_ZPASS = 2,       /* z-pass of a step */
   SPIN1_K_LOCAL = 3,       /* stand-alone local update (closing half step) */

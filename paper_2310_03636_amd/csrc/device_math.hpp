@@ -1,7 +1,7 @@
 // Device building blocks of the spin-1 split-step library (gfx950).
 //
 //  * Cx<Real>        interleaved complex value (complex64 / complex128 layout)
-//  * dft<Real, R>    in-register radix-R DFT, R = 1, 2, 4, 8, 16
+//  * dft<Real, R>    in-register radix-R DFT, R = 1, 2, 4, 8, 16, 32
 //  * fft_pencil      Stockham autosort FFT of one pencil of length N, held as
 //                    R values per thread (thread t owns indices t + e*N/R),
 //                    exchanging through LDS between stages
@@ -93,41 +93,40 @@ __device__ __forceinline__ Real dot_const(Real x, double c, Real y, double s) {
 // In-register DFT: out[k] = sum_r v[r] exp(-2 pi i r k / R), radix-2 split
 // into even and odd halves, constant twiddles specialised at compile time.
 // ---------------------------------------------------------------------------
-// cos and sin of pi*k/8, k = 0..7
-__device__ constexpr double kCos16[8] = {1.0,
-                                         0.92387953251128675613,
-                                         0.70710678118654752440,
-                                         0.38268343236508977173,
-                                         0.0,
-                                         -0.38268343236508977173,
-                                         -0.70710678118654752440,
-                                         -0.92387953251128675613};
-__device__ constexpr double kSin16[8] = {0.0,
-                                         0.38268343236508977173,
-                                         0.70710678118654752440,
-                                         0.92387953251128675613,
-                                         1.0,
-                                         0.92387953251128675613,
-                                         0.70710678118654752440,
-                                         0.38268343236508977173};
+// cos(pi k / 16), k = 0..8; the other angles of a radix <= 32 DFT follow by
+// symmetry (cos(pi (16 - k)/16) = -cos(pi k/16), sin(pi k/16) = cos(pi (8 - k)/16))
+__device__ constexpr double kCos32[9] = {1.0,
+                                         0.98078528040323044912618223613424,
+                                         0.92387953251128675612818318939679,
+                                         0.83146961230254523707878837761791,
+                                         0.70710678118654752440084436210485,
+                                         0.55557023301960222474283081394853,
+                                         0.38268343236508977172845998403040,
+                                         0.19509032201612826784828486847702,
+                                         0.0};
 
-// v * exp(-2 pi i K / R); the irrational constants go through mul_const /
-// dot_const so the single-precision path uses them at full FP64 accuracy
+constexpr double cos_pi16(int i) { return i <= 8 ? kCos32[i] : -kCos32[16 - i]; }
+constexpr double sin_pi16(int i) { return i <= 8 ? kCos32[8 - i] : kCos32[i - 8]; }
+
+// v * exp(-2 pi i K / R) = v * exp(-i pi I / 16), I = K * 32 / R < 16; the
+// irrational constants go through mul_const / dot_const so the single-
+// precision path uses them at full FP64 accuracy
 template <typename Real, int R, int K>
 __device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v) {
-  constexpr int I = K * (16 / R);
+  static_assert(R <= 32 && 2 * K < R, "twiddle of a radix <= 32 half");
+  constexpr int I = K * (32 / R);
   constexpr double h = 0.70710678118654752440;
   if constexpr (I == 0) {
     return v;
-  } else if constexpr (I == 4) {
+  } else if constexpr (I == 8) {
     return {v.im, -v.re};
-  } else if constexpr (I == 2) {
+  } else if constexpr (I == 4) {
     return {mul_const<Real>(v.re + v.im, h), mul_const<Real>(v.im - v.re, h)};
-  } else if constexpr (I == 6) {
+  } else if constexpr (I == 12) {
     return {mul_const<Real>(v.im - v.re, h), -mul_const<Real>(v.re + v.im, h)};
   } else {
-    constexpr double c = kCos16[I];
-    constexpr double s = kSin16[I];
+    constexpr double c = cos_pi16(I);
+    constexpr double s = sin_pi16(I);
     return {dot_const<Real>(v.re, c, v.im, s), dot_const<Real>(v.im, c, v.re, -s)};
   }
 }
@@ -144,7 +143,7 @@ __device__ __forceinline__ void dft_combine(Cx<Real>* v, const Cx<Real>* e, cons
 
 template <typename Real, int R>
 __device__ __forceinline__ void dft(Cx<Real>* v) {
-  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "radix");
   if constexpr (R == 2) {
     const Cx<Real> a = v[0], b = v[1];
     v[0] = a + b;
@@ -180,8 +179,45 @@ struct StageRadix {
   static constexpr int value = ((N / Ns) % R == 0) ? R : (N / Ns);
 };
 
-template <typename Real, int N, int R, int Ns, class Lds>
-__device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw) {
+// Twiddle w^(j r N/(Ns Rs)) of butterfly j, element r, in the stage with
+// sub-transform size Ns and radix Rs.  Default: TW indexable by the exponent
+// m < N (a pointer to the full table, or HalfTwiddles).
+template <int N, int Ns, int Rs, class TW>
+__device__ __forceinline__ auto tw_at(const TW& tw, int j, int r) {
+  return tw[j * r * (N / (Ns * Rs))];
+}
+
+// Twiddles laid out stage by stage: for the stage with Ns (a power of R) the
+// entries (r - 1) * Ns + j, r = 1..Rs-1, j < Ns, follow each other from offset
+// Ns - R (the earlier stages hold (R - 1)(R + R^2 + ... + Ns/R) entries); N - R
+// entries in all.  The lanes of a pencil read consecutive entries, which keeps
+// LDS reads free of bank conflicts where the exponent-indexed table puts the
+// butterflies of a stage N/(Ns Rs) entries apart.
+template <typename Real, int N, int R>
+struct StagedTwiddles {
+  const TabEntry<Real>* t;
+  static constexpr int SIZE = N - R;
+  // exponent of entry i (table construction)
+  __device__ static __forceinline__ int exponent(int i) {
+    int ns = R;
+    while (i >= ns * ((N / ns) % R == 0 ? R - 1 : N / ns - 1)) {
+      i -= ns * ((N / ns) % R == 0 ? R - 1 : N / ns - 1);
+      ns *= R;
+    }
+    const int rs = (N / ns) % R == 0 ? R : N / ns;
+    const int r = i / ns + 1, j = i % ns;
+    return j * r * (N / (ns * rs));
+  }
+};
+template <int N, int Ns, int Rs, typename Real, int R>
+__device__ __forceinline__ TabEntry<Real> tw_at(const StagedTwiddles<Real, N, R>& tw, int j, int r) {
+  static_assert(Ns >= R, "the first stage has no twiddles");
+  return tw.t[(Ns - R) + (r - 1) * Ns + j];
+}
+
+// TW: see tw_at
+template <typename Real, int N, int R, int Ns, class Lds, class TW>
+__device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const TW& tw) {
   if constexpr (Ns < N) {
     constexpr int Rs = StageRadix<N, R, Ns>::value;
     constexpr int U = R / Rs;
@@ -197,7 +233,7 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const T
       for (int r = 0; r < Rs; ++r) w[r] = v[u + r * U];
       if constexpr (Ns > 1) {
 #pragma unroll
-        for (int r = 1; r < Rs; ++r) w[r] = mul_tab(w[r], tw[j * r * (N / (Ns * Rs))]);
+        for (int r = 1; r < Rs; ++r) w[r] = mul_tab(w[r], tw_at<N, Ns, Rs>(tw, j, r));
       }
       dft<Real, Rs>(w);
       if constexpr (last) {
@@ -219,21 +255,58 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const T
   }
 }
 
-template <typename Real, int N, int R, class Lds>
-__device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw) {
+template <typename Real, int N, int R, class Lds, class TW>
+__device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const TW& tw) {
   static_assert((N & (N - 1)) == 0 && N >= R, "N must be a power of two >= R");
   fft_stages<Real, N, R, 1>(v, t, lds, tw);
 }
 
 // Forward FFT, multiply by ph[k] (which carries the 1/N of the inverse),
 // inverse FFT through conj(FFT(conj(.))).  ph is in natural k order.
-template <typename Real, int N, int R, class Lds>
-__device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const TabEntry<Real>* __restrict__ tw,
+template <typename Real, int N, int R, class Lds, class TW>
+__device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
                                                const TabEntry<Real>* __restrict__ ph) {
   constexpr int T = N / R;
   fft_pencil<Real, N, R>(v, t, lds, tw);
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = conj(mul_tab(v[e], ph[t + e * T]));
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = conj(v[e]);
+}
+
+// Twiddles exp(-2 pi i m / N) from the half table m <= N/2 (conjugate symmetry
+// w^(N-m) = conj(w^m)), for kernels that keep their tables in LDS.
+template <typename Real, int N>
+struct HalfTwiddles {
+  const TabEntry<Real>* t;
+  __device__ __forceinline__ TabEntry<Real> operator[](int m) const {
+    if (m <= N / 2) return t[m];
+    TabEntry<Real> w = t[N - m];
+    w.hi = -w.hi;
+    if constexpr (sizeof(Real) == 4) w.li = -w.li;
+    return w;
+  }
+};
+
+// Forward FFT, multiply by ph0[min(k, N-k)] (the kinetic phase with 1/N, even
+// in k) and, when zq is given, by the uniform factor *zq, inverse FFT.
+// Element e of thread t is k = t + e*N/R: below N/2 for e < R/2, at or above
+// it otherwise, so the mirror choice is static.
+template <typename Real, int N, int R, class Lds, class TW>
+__device__ __forceinline__ void fft_halfphase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
+                                                   const TabEntry<Real>* __restrict__ ph0,
+                                                   const TabEntry<Real>* zq) {
+  constexpr int T = N / R;
+  static_assert(R >= 2, "the static mirror split needs two halves");
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const int k = e < R / 2 ? t + e * T : N - t - e * T;
+    Cx<Real> x = mul_tab(v[e], ph0[k]);
+    if (zq) x = mul_tab(x, *zq);
+    v[e] = conj(x);
+  }
   fft_pencil<Real, N, R>(v, t, lds, tw);
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = conj(v[e]);

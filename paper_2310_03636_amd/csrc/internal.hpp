@@ -64,6 +64,10 @@ hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint6
 hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant = 0);
 hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant = 0);
 int step_variants();
+// 1D: K split steps of one pencil per workgroup in one launch (open_half: the
+// first step opens with R(dt/2) instead of R(dt); close_half: closing R(dt/2))
+hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
+                            bool close_half);
 hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
 hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
                       const int32_t* offs, int nbins, double* out);

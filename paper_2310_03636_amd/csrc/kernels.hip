@@ -43,12 +43,16 @@ struct XCfg {
 template <int N, typename Real, int V = 0>
 struct SCfg {
   static constexpr int R0 = N <= 8 ? N : (N <= 128 ? 8 : 16);
-  static constexpr int R = (V == 2 && N >= 64) ? 8 : R0;
+  // FP32 columns of 512: radix 32 by default (two stages, one LDS exchange per
+  // transform), variant 1 is radix 16 on the full 16-column tile
+  static constexpr bool C512 = N == 512 && sizeof(Real) == 4;
+  static constexpr bool R32 = V == 0 && C512;
+  static constexpr int R = (V == 2 && N >= 64) ? 8 : (R32 ? 32 : R0);
   static constexpr int T = N / R;
   static constexpr int CB = int(sizeof(Cx<Real>));
   static constexpr int TXRAW = 65536 / (N * CB);
   static constexpr int TX0 = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
-  static constexpr int TX1 = (V == 1 && TX0 > 4) ? TX0 / 2 : TX0;
+  static constexpr int TX1 = (V == 1 && TX0 > 4 && !C512) ? TX0 / 2 : TX0;
   // keep workgroups within 1024 threads
   static constexpr int TX = TX1 * T > 1024 ? 1024 / T : TX1;
   static constexpr int THREADS = TX * T;
@@ -130,9 +134,10 @@ struct RowLds {
 // spreads rows that differ by a power of two over different banks.
 template <typename Real, int TX>
 struct ColLds {
+  static constexpr int PITCH = TX >= 16 ? TX : TX + 1;
   Cx<Real>* col;
-  __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * (TX + 1)] = v; }
-  __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * (TX + 1)]; }
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * PITCH] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * PITCH]; }
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
@@ -364,9 +369,9 @@ template <typename Real, int N, int V>
 __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
   constexpr int R = SCfg<N, Real, V>::R, T = SCfg<N, Real, V>::T, TX = SCfg<N, Real, V>::TX;
-  __shared__ C lds[N * (TX + 1)];
+  __shared__ C lds[N * ColLds<Real, TX>::PITCH];
   __shared__ TabEntry<Real> tw[N];
-  __shared__ TabEntry<Real> ph[N];
+  __shared__ TabEntry<Real> ph[N / 2 + 1];  // the phase is even in k
   const int c = threadIdx.x % TX;
   const int t = threadIdx.x / TX;
   const int64_t tiles = a.inner / TX;
@@ -374,10 +379,8 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-      tw[i] = gtw[i];
-      ph[i] = gph[i];
-    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i <= N / 2; i += blockDim.x) ph[i] = gph[i];
     __syncthreads();
   }
   // item -> (field f, outer o, tile): shifts, all three extents are powers of two
@@ -409,7 +412,7 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
 #pragma unroll
       for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
     }
-    fft_phase_ifft<Real, N, R>(v, t, L, tw, ph);
+    fft_halfphase_ifft<Real, N, R>(v, t, L, tw, ph, static_cast<const TabEntry<Real>*>(nullptr));
 #pragma unroll
     for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
   }
@@ -421,7 +424,8 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real, V>::R, T = XCfg<N, Real, V>::T, P = XCfg<N, Real, V>::P;
   __shared__ C lds[P * RowPad<N, T>::ROW];
-  __shared__ TabEntry<Real> stw[N];
+  using TW = StagedTwiddles<Real, N, R>;
+  __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
   // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
   __shared__ TabEntry<Real> ph[2 * N];
   const int t = threadIdx.x % T;
@@ -430,7 +434,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) stw[i] = gtw[i];
+    for (int i = threadIdx.x; i < TW::SIZE; i += blockDim.x) stw[i] = gtw[TW::exponent(i)];
     for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) ph[i] = gph[i];
     __syncthreads();
   }
@@ -476,7 +480,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
       }
     }
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, stw, ph + (m == 1 ? N : 0));
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, TW{stw}, ph + (m == 1 ? N : 0));
     if (a.tau_post != 0.0) {
       const Real tau = Real(a.tau_post);
 #pragma unroll
@@ -500,6 +504,92 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
 }
  }
 
+__device__ __forceinline__ void store_tab(TabEntry<float>* p, double re, double im) {
+  const float hr = float(re), hi = float(im);
+  *p = TabEntry<float>{hr, hi, float(re - double(hr)), float(im - double(hi))};
+}
+__device__ __forceinline__ void store_tab(TabEntry<double>* p, double re, double im) { *p = TabEntry<double>{re, im}; }
+
+
+// --------------------------------------------------------------------------
+// 1D: several steps per launch.  A 1D sample is one pencil, so a workgroup
+// can keep it in registers for K consecutive split steps with no HBM traffic
+// in between: load, K x [R(tau) -> FFT -> phase -> inverse FFT], optional
+// closing R(dt/2), store.  One pencil per workgroup (the sample count is the
+// parallelism); tables in LDS: twiddles (half table for N = 4096) and the
+// kinetic phase for k <= N/2 (it is even in k), the Zeeman factor
+// exp(-i q dt) applied separately to m = +-1.
+// --------------------------------------------------------------------------
+template <int N, typename Real>
+struct MultiCfg {
+  static constexpr int R = XCfg<N, Real>::R;
+  static constexpr int T = N / R;
+  static constexpr bool HALF_TW = N >= 4096;
+  static constexpr int TW_N = HALF_TW ? N / 2 + 1 : N;
+};
+
+template <typename Real, int N>
+__global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs a, int K, double dt, int open_half,
+                                                                       int close_half) {
+  using C = Cx<Real>;
+  using Cfg = MultiCfg<N, Real>;
+  constexpr int R = Cfg::R, T = Cfg::T;
+  __shared__ C lds[RowPad<N, T>::ROW];
+  __shared__ TabEntry<Real> stw[Cfg::TW_N];
+  __shared__ TabEntry<Real> ph0[N / 2 + 1];
+  __shared__ TabEntry<Real> zq;
+  const int t = threadIdx.x;
+  {
+    const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
+    const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph) + N;  // m = 0 row
+    for (int i = t; i < Cfg::TW_N; i += T) stw[i] = gtw[i];
+    for (int i = t; i <= N / 2; i += T) ph0[i] = gph[i];
+    if (t == 0) {
+      double sn, cs;
+      sincos(a.q * dt, &sn, &cs);
+      store_tab(&zq, cs, -sn);
+    }
+    __syncthreads();
+  }
+  RowLds<Real, N, T, (T <= 64)> L{lds};
+  C* psi = static_cast<C*>(a.psi) + int64_t(blockIdx.x) * 3 * a.sites + t;
+  C v[3][R];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[m][e] = psi[m * a.sites + e * T];
+  const Real c0 = Real(a.c0), c1 = Real(a.c1);
+  auto local_all = [&](Real tau) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      C site[3] = {v[0][e], v[1][e], v[2][e]};
+      local_update(site, tau, c0, c1);
+      v[0][e] = site[0];
+      v[1][e] = site[1];
+      v[2][e] = site[2];
+    }
+  };
+  for (int k = 0; k < K; ++k) {
+    local_all(Real((k == 0 && open_half) ? 0.5 * dt : dt));
+    if constexpr (Cfg::HALF_TW) {
+      const HalfTwiddles<Real, N> tw{stw};
+      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
+      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
+      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
+    } else {
+      const TabEntry<Real>* tw = stw;
+      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
+      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
+      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
+    }
+  }
+  if (close_half) local_all(Real(0.5 * dt));
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int e = 0; e < R; ++e) psi[m * a.sites + e * T] = v[m][e];
+}
+
 // --------------------------------------------------------------------------
 // local update alone (closing half step of multi-dimensional grids)
 // --------------------------------------------------------------------------
@@ -522,12 +612,6 @@ __global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sit
 // ph[m][k] = exp(-i (k^2/2 + q m^2) dt) / N (m = +1, 0, -1 when ncomp = 3)
 // tw[k]    = exp(-2 pi i k / N)
 // --------------------------------------------------------------------------
-__device__ __forceinline__ void store_tab(TabEntry<float>* p, double re, double im) {
-  const float hr = float(re), hi = float(im);
-  *p = TabEntry<float>{hr, hi, float(re - double(hr)), float(im - double(hi))};
-}
-__device__ __forceinline__ void store_tab(TabEntry<double>* p, double re, double im) { *p = TabEntry<double>{re, im}; }
-
 template <typename Real>
 __global__ void k_tables(TabEntry<Real>* ph, TabEntry<Real>* tw, int n, int ncomp, double dt, double q, double dx) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -945,6 +1029,36 @@ hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassAr
 }
 
 int step_variants() { return kStepVariants; }
+
+template <typename Real, int N>
+static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double dt, bool open_half, bool close_half) {
+  hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
+                     int(open_half), int(close_half));
+  return hipGetLastError();
+}
+
+template <typename Real>
+static hipError_t x1d_multi_t(hipStream_t st, int n, const XPassArgs& a, int K, double dt, bool oh, bool ch) {
+  switch (n) {
+    case 8: return x1d_multi_n<Real, 8>(st, a, K, dt, oh, ch);
+    case 16: return x1d_multi_n<Real, 16>(st, a, K, dt, oh, ch);
+    case 32: return x1d_multi_n<Real, 32>(st, a, K, dt, oh, ch);
+    case 64: return x1d_multi_n<Real, 64>(st, a, K, dt, oh, ch);
+    case 128: return x1d_multi_n<Real, 128>(st, a, K, dt, oh, ch);
+    case 256: return x1d_multi_n<Real, 256>(st, a, K, dt, oh, ch);
+    case 512: return x1d_multi_n<Real, 512>(st, a, K, dt, oh, ch);
+    case 1024: return x1d_multi_n<Real, 1024>(st, a, K, dt, oh, ch);
+    case 2048: return x1d_multi_n<Real, 2048>(st, a, K, dt, oh, ch);
+    case 4096: return x1d_multi_n<Real, 4096>(st, a, K, dt, oh, ch);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
+                            bool close_half) {
+  return dbl ? x1d_multi_t<double>(st, n, a, K, dt, open_half, close_half)
+             : x1d_multi_t<float>(st, n, a, K, dt, open_half, close_half);
+}
 
 static unsigned grid_for(int64_t work, int threads) {
   int64_t b = (work + threads - 1) / threads;

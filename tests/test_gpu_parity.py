@@ -63,16 +63,63 @@ def test_init_wigner_groups_use_group_counter(lib):
 
 
 # ------------------------------------------------------------------ one step, every size
+@pytest.mark.parametrize("per_launch", [1, 64])
 @pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
-def test_one_step_1d_all_sizes(lib, n):
+def test_one_step_1d_all_sizes(lib, n, per_launch):
+    """per_launch 1: the x-pass kernel; 64: the 1D multi-step kernel."""
     grid = (1, (n,), 0.5, 5)
     og = O.Grid(1, (n,), 0.5, 5)
     psi0 = random_field(n, og.shape, noise=0.4)
     ref = O.strang_step(psi0, 0.01, oparams(P1), og)
-    got = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=1).fields()[0]
-    assert rel(got, ref) < 1e-13
-    got32 = run_gpu(lib, grid, P1, "c64", psi0=psi0, nsteps=1).fields()[0]
-    assert rel(got32, ref) < 2e-6
+    for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
+        sim = lib.Sim([grid], P1, dtype=dtype)
+        sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, per_launch)
+        sim.set_fields([psi0])
+        sim.step(1, 0.01)
+        assert rel(sim.fields()[0], ref) < tol, dtype
+
+
+@pytest.mark.parametrize("n", [8, 64, 256, 1024, 2048, 4096])
+def test_multi_step_1d_chunks_match_oracle(lib, n):
+    """23 steps as launches of 7, 7, 7 and 2 steps (first opens, last closes
+    with a half step) against the oracle and against one launch per step."""
+    grid = (1, (n,), 0.5, 3)
+    og = O.Grid(1, (n,), 0.5, 3)
+    psi0 = random_field(n + 1, og.shape, noise=0.4)
+    ref = O.evolve(psi0, 23, 0.01, oparams(P1), og)
+    for dtype, tol, tol_pair in (("c128", 1e-12, 1e-13), ("c64", 1e-5, 5e-6)):
+        out = {}
+        for per_launch in (1, 7):
+            sim = lib.Sim([grid], P1, dtype=dtype)
+            sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, per_launch)
+            sim.set_fields([psi0])
+            sim.step(23, 0.01)
+            out[per_launch] = sim.fields()[0]
+            assert rel(out[per_launch], ref) < tol, (dtype, per_launch)
+        assert rel(out[7], out[1]) < tol_pair, dtype
+
+
+def test_multi_step_1d_graph_and_option(lib):
+    """Changing the steps per launch retires captured graphs; replays of the
+    multi-step launches equal direct launches."""
+    grid = (1, (512,), 0.5, 6)
+    a = lib.Sim([grid], P1, dtype="c64")
+    b = lib.Sim([grid], P1, dtype="c64")
+    b.set_option(lib.OPT_GRAPHS, 0)
+    a.init_wigner(12)
+    b.init_wigner(12)
+    for rep in range(3):
+        a.step(40, 0.02)
+        b.step(40, 0.02)
+        assert np.array_equal(a.fields()[0], b.fields()[0]), rep
+    a.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 1)
+    b.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 1)
+    a.step(40, 0.02)
+    b.step(40, 0.02)
+    assert np.array_equal(a.fields()[0], b.fields()[0])
+    for bad in (0, 1025):
+        with pytest.raises(lib.Spin1Error):
+            a.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, bad)
 
 
 @pytest.mark.parametrize("ny", [8, 16, 32, 64, 128, 256, 512, 1024])
