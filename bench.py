@@ -218,10 +218,12 @@ def profile_pass():
     w = WORKLOAD
     sim = spin1.Sim([(w["dim"], w["n"], w["dx"], w["samples"])], w["params"], dtype="c64")
     sim.init_wigner(w["seed"])
+    variants = sim.autotune(reps=2)  # the same choice as the timed run
     sim.set_option(spin1.OPT_GRAPHS, 0)
     sim.step(3, w["dt"])
     sim.synchronize()
     sim.close()
+    print("profile pass variants: %s" % json.dumps(variants), flush=True)
     n = 64 * 512 * 512 * 3  # complex64 values of one field: 402.65 MB
     src = torch.ones(n, dtype=torch.complex64, device="cuda")
     dst = torch.empty_like(src)

@@ -185,9 +185,10 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   synchronized time.
  * SPIN1_OPT_STEPS_PER_LAUNCH_1D: 1D groups run up to this many consecutive
  *   split steps in one launch, each sample held on chip between steps
- *   (default 64, range 1..1024); 1 = one x-pass launch per step, as for
- *   2D/3D groups.  The result is the same map either way (same arithmetic,
- *   different kernel). */
+ *   (range 1..1024); 1 = one x-pass launch per step, as for 2D/3D groups;
+ *   0 (default) = automatic: 64 for Nx <= 1024, 1 above (where a sample's
+ *   three components no longer fit one workgroup's registers).  The result
+ *   is the same map either way (same arithmetic, different kernel). */
 enum spin1_option { SPIN1_OPT_GRAPHS = 0, SPIN1_OPT_GRAPH_MAX_STEPS = 1, SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 

@@ -214,7 +214,7 @@ struct spin1_ctx {
   // captured step sequences: (steps, dt) of the current binding and couplings
   bool use_graphs = true;
   int64_t graph_max_steps = 1024;
-  int steps_per_launch_1d = 64;
+  int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -392,12 +392,19 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
 // 1D groups with more than one step per launch: consecutive chunks of up to
 // steps_per_launch_1d steps, the first opening with R(dt/2), the last closing
 // with R(dt/2), exactly the sequence of the per-step passes.
-bool multi_1d(const spin1_ctx* ctx, const GroupState& G) { return G.geo.dim == 1 && ctx->steps_per_launch_1d > 1; }
+int steps_per_launch(const spin1_ctx* ctx, const GroupState& G) {
+  if (G.geo.dim != 1) return 1;
+  if (ctx->steps_per_launch_1d > 0) return ctx->steps_per_launch_1d;
+  return G.geo.n[0] <= 1024 ? 64 : 1;
+}
+
+bool multi_1d(const spin1_ctx* ctx, const GroupState& G) { return steps_per_launch(ctx, G) > 1; }
 
 int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double dt) {
   XPassArgs xa = xargs(ctx, G);
-  for (int64_t i0 = 0; i0 < n; i0 += ctx->steps_per_launch_1d) {
-    const int k = int(n - i0 < ctx->steps_per_launch_1d ? n - i0 : ctx->steps_per_launch_1d);
+  const int per = steps_per_launch(ctx, G);
+  for (int64_t i0 = 0; i0 < n; i0 += per) {
+    const int k = int(n - i0 < per ? n - i0 : per);
     hipError_t e;
     {
       Prof pr(ctx, SPIN1_K_XPASS);
@@ -945,7 +952,7 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
       ctx->graph_max_steps = value;
       return SPIN1_OK;
     case SPIN1_OPT_STEPS_PER_LAUNCH_1D:
-      if (value < 1 || value > 1024) return fail(SPIN1_EINVAL, "1D steps per launch must be in 1..1024");
+      if (value < 0 || value > 1024) return fail(SPIN1_EINVAL, "1D steps per launch must be in 0..1024");
       ctx->steps_per_launch_1d = int(value);
       ctx->version++;  // captured graphs hold the old launch pattern
       return SPIN1_OK;

@@ -39,20 +39,23 @@ struct XCfg {
 };
 
 // strided pass: radix R, TX adjacent columns per workgroup (TX x N/R threads).
-// Step-pass variants: V = 0 the default, V = 1 half the columns, V = 2 radix 8.
+// Step-pass variants: V = 0 the default, V = 1 half the columns (radix 16 on 512
+// and radix 32 on 1024 for FP32), V = 2 radix 8.
 template <int N, typename Real, int V = 0>
 struct SCfg {
   static constexpr int R0 = N <= 8 ? N : (N <= 128 ? 8 : 16);
   // FP32 columns of 512: radix 32 by default (two stages, one LDS exchange per
   // transform), variant 1 is radix 16 on the full 16-column tile
+  // and variant 1 of FP32 columns of 1024 is radix 32 on a 16-column tile
   static constexpr bool C512 = N == 512 && sizeof(Real) == 4;
-  static constexpr bool R32 = V == 0 && C512;
+  static constexpr bool C1024 = N == 1024 && sizeof(Real) == 4;
+  static constexpr bool R32 = (V == 0 && C512) || (V == 1 && C1024);
   static constexpr int R = (V == 2 && N >= 64) ? 8 : (R32 ? 32 : R0);
   static constexpr int T = N / R;
   static constexpr int CB = int(sizeof(Cx<Real>));
   static constexpr int TXRAW = 65536 / (N * CB);
   static constexpr int TX0 = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
-  static constexpr int TX1 = (V == 1 && TX0 > 4 && !C512) ? TX0 / 2 : TX0;
+  static constexpr int TX1 = (V == 1 && C1024) ? 16 : ((V == 1 && TX0 > 4 && !C512) ? TX0 / 2 : TX0);
   // keep workgroups within 1024 threads
   static constexpr int TX = TX1 * T > 1024 ? 1024 / T : TX1;
   static constexpr int THREADS = TX * T;

@@ -117,7 +117,12 @@ def test_multi_step_1d_graph_and_option(lib):
     a.step(40, 0.02)
     b.step(40, 0.02)
     assert np.array_equal(a.fields()[0], b.fields()[0])
-    for bad in (0, 1025):
+    a.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 0)  # automatic
+    b.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 0)
+    a.step(40, 0.02)
+    b.step(40, 0.02)
+    assert np.array_equal(a.fields()[0], b.fields()[0])
+    for bad in (-1, 1025):
         with pytest.raises(lib.Spin1Error):
             a.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, bad)
 
