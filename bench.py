@@ -150,7 +150,10 @@ OTHER_CONFIGS = {
     "1d_256_s4_c128": dict(groups=[(1, (256,), 0.5, 4)], dtype="c128", dt=0.01, steps=1000,
                            params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1001),
     "3d_256_s8_c64": dict(groups=[(3, (256, 256, 256), 0.5, 8)], dtype="c64", dt=0.02, steps=20,
-                          params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003),
+                          params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003, log=True),
+    # six times the main batch (2.4 GB of field, beyond the 256 MB last-level cache)
+    "2d_512_s384_c64": dict(groups=[(2, (512, 512), 0.5, 384)], dtype="c64", dt=0.02, steps=20,
+                            params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002),
     "uneven_c64": dict(groups=[(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
                                (2, (1024, 1024), 0.5, 4)], dtype="c64", dt=0.02, steps=100,
                        params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1004),
@@ -180,6 +183,19 @@ def other_configs():
         out[name] = {"value": sites * c["steps"] / (ms / 1e3), "unit": "site-steps/s", "steps": c["steps"],
                      "ms_per_split_step": ms / c["steps"], "dtype": c["dtype"], "variants": tuned,
                      "norm_sample0": float(obs[0, 0])}
+        if c.get("log"):
+            # the same steps with the per-step FP64 (N, F_z, E) log of group 0
+            e0.record(sim.stream)
+            log = sim.step_observed(c["steps"], c["dt"])
+            e1.record(sim.stream)
+            sim.synchronize()
+            ms_log = e0.elapsed_time(e1)
+            n_, fz_, en_ = log[:, :, 0], log[:, :, 1], log[:, :, 2]
+            out[name]["logged"] = {
+                "value": sites * c["steps"] / (ms_log / 1e3), "unit": "site-steps/s",
+                "max_rel_norm_change": float(abs(n_ / n_[0] - 1).max()),
+                "max_abs_fz_change_per_norm": float((abs(fz_ - fz_[0]) / n_[0]).max()),
+                "max_rel_energy_change": float((abs(en_ / en_[0] - 1)).max())}
         sim.close()
         del sim
         torch.cuda.empty_cache()

@@ -134,6 +134,17 @@ SPIN1_API int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins
  * E the energy whose Wirtinger derivative is the right-hand side of Eq. (2). */
 SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
 
+/* spin1_step(n, dt) that also logs, for group `group`, the FP64 (N, F_z, E)
+ * of every step: obs_dev is a device array [n][S][3] of double, row i being
+ * the observables of R(dt/2) psi(t + i dt), the state the kinetic sub-step of
+ * step i starts from (summed inside the step passes, no extra field pass).
+ * N and F_z equal those of psi(t + i dt) exactly (R conserves n and F at every
+ * site); E differs from E(psi(t + i dt)) by O(dt) and carries no drift of its
+ * own.  Direct launches (no graph); 1D groups take one x-pass launch per step
+ * in this call.  Errors as spin1_step, and SPIN1_EINVAL for a bad group or a
+ * NULL obs_dev. */
+SPIN1_API int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, double* obs_dev);
+
 /* Apply the exact local update R(tau) alone to every bound field (Eqs. (4)-(5)
  * combined, q excluded). */
 SPIN1_API int spin1_local_update(spin1_ctx* ctx, double tau);

@@ -701,6 +701,71 @@ int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
   return SPIN1_OK;
 }
 
+// One step of group G with the observables of the state its kinetic sub-step
+// starts from summed inside the passes and finished into obs (S x 3).
+static int enqueue_group_step_logged(spin1_ctx* ctx, const GroupState& G, double dt, double tau_open,
+                                     double tau_close, double* obs) {
+  XPassArgs xa = xargs(ctx, G);
+  xa.tau_pre = tau_open;
+  xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
+  xa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[0]));
+  hipError_t e;
+  {
+    Prof pr(ctx, SPIN1_K_XPASS);
+    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP_LOG, G.geo.n[0], xa);
+  }
+  if (e != hipSuccess) return hip_fail(e, "logged x-pass");
+  for (int a = 1; a < G.geo.dim; ++a) {
+    SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
+    sa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[a]));
+    {
+      Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
+      e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP_LOG, G.geo.n[a], sa);
+    }
+    if (e != hipSuccess) return hip_fail(e, "logged strided pass");
+  }
+  {
+    const double* py = G.geo.dim > 1 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[1])) : nullptr;
+    const double* pz = G.geo.dim > 2 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[2])) : nullptr;
+    Prof pr(ctx, SPIN1_K_OBSERVABLES);
+    e = launch_obs_finish(ctx->stream, G.geo.S, reinterpret_cast<const double*>(at(ctx, G.lay.part[0])), G.geo.rows,
+                          py, G.lay.nblk[1] / G.geo.S, pz, G.lay.nblk[2] / G.geo.S, cell_of(G.geo), obs);
+  }
+  if (e != hipSuccess) return hip_fail(e, "logged observables finish");
+  if (G.geo.dim > 1 && tau_close != 0.0) {
+    {
+      Prof pr(ctx, SPIN1_K_LOCAL);
+      e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "closing local update");
+  }
+  return SPIN1_OK;
+}
+
+int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, double* obs_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!obs_dev) return fail(SPIN1_EINVAL, "obs_dev is NULL");
+  if (n < 0) return fail(SPIN1_EINVAL, "n must be >= 0");
+  if (!isfinite(dt)) return fail(SPIN1_EINVAL, "dt must be finite");
+  if (n == 0) return SPIN1_OK;
+  if (!ctx->tab_valid || ctx->tab_dt != dt || ctx->tab_q != ctx->p.q)
+    if ((rc = make_tables(ctx, dt))) return rc;
+  const int64_t S = ctx->groups[size_t(group)].geo.S;
+  for (int64_t i = 0; i < n; ++i) {
+    const double pre = i == 0 ? 0.5 * dt : dt;
+    const double close = i == n - 1 ? 0.5 * dt : 0.0;
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
+      const GroupState& G = ctx->groups[g];
+      rc = int64_t(g) == group ? enqueue_group_step_logged(ctx, G, dt, pre, close, obs_dev + i * S * 3)
+                               : enqueue_group_step(ctx, G, G.psi, dt, pre, close);
+      if (rc) return rc;
+    }
+  }
+  return SPIN1_OK;
+}
+
 // ---------------------------------------------------------------------------
 // reverse mode
 // ---------------------------------------------------------------------------

@@ -22,7 +22,9 @@ struct Geom {
 int spass_tx(int n, bool dbl);
 
 // Kernel modes
-enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3 };
+// MODE_STEP_LOG: a step pass that also writes the FP64 partial sums of
+// MODE_MEASURE for the state its kinetic sub-step starts from
+enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3, MODE_STEP_LOG = 4 };
 
 struct XPassArgs {
   void* psi;        // field base [S][3][rows][Nx] (STEP, MEASURE, SF*)

@@ -175,6 +175,54 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return s;
 }
 
+// FP64 site sums of the observables: n, F_z and the local energy density
+// c0/2 n^2 + c1/2 |F|^2 + q (|psi_1|^2 + |psi_-1|^2) (acc[0..2])
+template <typename Real>
+__device__ __forceinline__ void site_sums(Cx<Real> p1, Cx<Real> p0, Cx<Real> pm, double c0, double c1, double q,
+                                          double* acc) {
+  const double d1 = double(norm2(p1)), d0 = double(norm2(p0)), dm = double(norm2(pm));
+  const Cx<Real> g = cmulc(p1, p0) + cmulc(p0, pm);
+  const double gre = double(g.re), gim = double(g.im);
+  const double n = d1 + d0 + dm, fz = d1 - dm;
+  const double f2 = 2.0 * (gre * gre + gim * gim) + fz * fz;
+  acc[0] += n;
+  acc[1] += fz;
+  acc[2] += 0.5 * c0 * n * n + 0.5 * c1 * f2 + q * (d1 + dm);
+}
+
+// Sum acc[0..3] over the T threads of pencil p and write the four totals to
+// out (thread t = 0 of an active pencil).  Every thread of the workgroup
+// calls it (it may synchronise the workgroup and reuse the pencil LDS).
+template <int T, typename Real>
+__device__ __forceinline__ void pencil_sums_out(const double* acc, Cx<Real>* lds, int p, int t, bool active,
+                                                double* out) {
+  double tot[4];
+  if constexpr (T <= 64) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tot[i] = lane_group_sum<T>(acc[i]);
+  } else {
+    constexpr int NW = T / 64;
+    double* scratch = reinterpret_cast<double*>(lds);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double w = lane_group_sum<64>(acc[i]);
+      if ((t & 63) == 0) scratch[(p * NW + (t >> 6)) * 4 + i] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double sacc = 0.0;
+      for (int w = 0; w < NW; ++w) sacc += scratch[(p * NW + w) * 4 + i];
+      tot[i] = sacc;
+    }
+  }
+  if (active && t == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = tot[i];
+  }
+}
+
 // --------------------------------------------------------------------------
 // x-pass: contiguous pencils, all 3 components of each site in one thread
 // --------------------------------------------------------------------------
@@ -199,7 +247,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
 #pragma unroll
     for (int e = 0; e < R; ++e) v[m][e] = active ? base[m * a.sites + e * T] : C{Real(0), Real(0)};
 
-  if constexpr (MODE == MODE_STEP) {
+  if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_LOG) {
     const Real c0 = Real(a.c0), c1 = Real(a.c1);
     if (a.tau_pre != 0.0) {
       const Real tau = Real(a.tau_pre);
@@ -213,8 +261,28 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
       }
     }
     const TabEntry<Real>* ph = static_cast<const TabEntry<Real>*>(a.ph);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (MODE == MODE_STEP_LOG) {
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
+      for (int e = 0; e < R; ++e) site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        fft_pencil<Real, N, R>(v[m], t, L, tw);
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const double kk = a.kscale * double(signed_k<N>(t + e * T));
+          acc[3] += 0.5 * kk * kk * double(norm2(v[m][e]));
+          v[m][e] = conj(mul_tab(v[m][e], ph[m * N + t + e * T]));
+        }
+        fft_pencil<Real, N, R>(v[m], t, L, tw);
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[m][e] = conj(v[m][e]);
+      }
+      acc[3] *= 1.0 / double(N);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
+    }
     if (a.tau_post != 0.0) {
       const Real tau = Real(a.tau_post);
 #pragma unroll
@@ -232,19 +300,11 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
 #pragma unroll
         for (int e = 0; e < R; ++e) base[m * a.sites + e * T] = v[m][e];
     }
+    if constexpr (MODE == MODE_STEP_LOG) pencil_sums_out<T>(acc, lds, p, t, active, a.part + pid * 4);
   } else if constexpr (MODE == MODE_MEASURE) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int e = 0; e < R; ++e) {
-      const double d1 = double(norm2(v[0][e])), d0 = double(norm2(v[1][e])), dm = double(norm2(v[2][e]));
-      const C g = cmulc(v[0][e], v[1][e]) + cmulc(v[1][e], v[2][e]);
-      const double gre = double(g.re), gim = double(g.im);
-      const double n = d1 + d0 + dm, fz = d1 - dm;
-      const double f2 = 2.0 * (gre * gre + gim * gim) + fz * fz;
-      acc[0] += n;
-      acc[1] += fz;
-      acc[2] += 0.5 * a.c0 * n * n + 0.5 * a.c1 * f2 + a.q * (d1 + dm);
-    }
+    for (int e = 0; e < R; ++e) site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       fft_pencil<Real, N, R>(v[m], t, L, tw);
@@ -255,31 +315,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
       }
     }
     acc[3] *= 1.0 / double(N);
-    double tot[4];
-    if constexpr (T <= 64) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) tot[i] = lane_group_sum<T>(acc[i]);
-    } else {
-      constexpr int NW = T / 64;
-      double* scratch = reinterpret_cast<double*>(lds);
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const double w = lane_group_sum<64>(acc[i]);
-        if ((t & 63) == 0) scratch[(p * NW + (t >> 6)) * 4 + i] = w;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double sacc = 0.0;
-        for (int w = 0; w < NW; ++w) sacc += scratch[(p * NW + w) * 4 + i];
-        tot[i] = sacc;
-      }
-    }
-    if (active && t == 0) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a.part[pid * 4 + i] = tot[i];
-    }
+    pencil_sums_out<T>(acc, lds, p, t, active, a.part + pid * 4);
   } else {
     // transverse spin F_perp = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1), forward FFT along x
     const Real r2 = Real(1.41421356237309504880);
@@ -333,6 +369,22 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
     fft_phase_ifft<Real, N, R>(v, t, L, tw, static_cast<const TabEntry<Real>*>(a.ph));
 #pragma unroll
     for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
+  } else if constexpr (MODE == MODE_STEP_LOG) {
+    const TabEntry<Real>* ph = static_cast<const TabEntry<Real>*>(a.ph);
+    fft_pencil<Real, N, R>(v, t, L, tw);
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      const double kk = a.kscale * double(signed_k<N>(t + e * T));
+      acc += 0.5 * kk * kk * double(norm2(v[e]));
+      v[e] = conj(mul_tab(v[e], ph[t + e * T]));
+    }
+    fft_pencil<Real, N, R>(v, t, L, tw);
+#pragma unroll
+    for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = conj(v[e]);
+    acc *= 1.0 / double(N);
+    const double tot = block_sum(acc, reinterpret_cast<double*>(lds));
+    if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
   } else if constexpr (MODE == MODE_MEASURE) {
     fft_pencil<Real, N, R>(v, t, L, tw);
     double acc = 0.0;
@@ -964,6 +1016,7 @@ static hipError_t xpass_t(hipStream_t st, int mode, int n, const XPassArgs& a, i
     case MODE_MEASURE: return xpass_mode<Real, MODE_MEASURE>(st, n, a, v);
     case MODE_SF: return xpass_mode<Real, MODE_SF>(st, n, a, v);
     case MODE_SF_POWER: return xpass_mode<Real, MODE_SF_POWER>(st, n, a, v);
+    case MODE_STEP_LOG: return xpass_mode<Real, MODE_STEP_LOG>(st, n, a, v);
   }
   return hipErrorInvalidValue;
 }
@@ -1023,6 +1076,7 @@ static hipError_t spass_t(hipStream_t st, int mode, int n, const SPassArgs& a, i
     case MODE_MEASURE: return spass_mode<Real, MODE_MEASURE>(st, n, a, v);
     case MODE_SF: return spass_mode<Real, MODE_SF>(st, n, a, v);
     case MODE_SF_POWER: return spass_mode<Real, MODE_SF_POWER>(st, n, a, v);
+    case MODE_STEP_LOG: return spass_mode<Real, MODE_STEP_LOG>(st, n, a, v);
   }
   return hipErrorInvalidValue;
 }

@@ -24,7 +24,7 @@ FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
     "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
-    "spin1_observables", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
+    "spin1_observables", "spin1_step_observed", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
     "spin1_num_variants", "spin1_autotune", "spin1_get_variant", "spin1_set_variant", "spin1_last_error",
 ]
@@ -78,6 +78,7 @@ def load():
         "spin1_step": (ctypes.c_int, [vp, i64, f64]),
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
+        "spin1_step_observed": (ctypes.c_int, [vp, i64, f64, i32, vp]),
         "spin1_local_update": (ctypes.c_int, [vp, f64]),
         "spin1_set_option": (ctypes.c_int, [vp, i32, i64]),
         "spin1_adjoint_workspace_bytes": (sz, [gp, i32, i64]),
@@ -198,6 +199,10 @@ def structure_factor(ctx, group, bins_ptr):
 
 def observables(ctx, group, obs_ptr):
     _check(load().spin1_observables(ctx, int(group), ctypes.c_void_p(int(obs_ptr))))
+
+
+def step_observed(ctx, n, dt, group, obs_ptr):
+    _check(load().spin1_step_observed(ctx, int(n), float(dt), int(group), ctypes.c_void_p(int(obs_ptr))))
 
 
 def local_update(ctx, tau):
@@ -439,6 +444,17 @@ class Sim:
         observables(self.ctx, group, out.data_ptr())
         with self.torch.cuda.stream(self.stream):
             return out.cpu().numpy()
+
+
+    def step_observed(self, n, dt, group=0):
+        """n steps, returning the per-step FP64 (N, F_z, E) of `group` as a
+        numpy array [n, S, 3] (row i: the state R(dt/2) psi(t + i dt))."""
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((max(int(n), 1), self.grids[group].samples, 3), dtype=self.torch.float64,
+                                   device=self.device)
+        step_observed(self.ctx, n, dt, group, out.data_ptr())
+        with self.torch.cuda.stream(self.stream):
+            return out[: int(n)].cpu().numpy()
 
 
 def _loss_from_bins(bins, target, mask):

@@ -276,6 +276,49 @@ def test_observables_match_oracle(lib, grid):
     assert np.allclose(got32, ref, rtol=2e-6, atol=2e-6 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 3), (2, (64, 32), 0.5, 2), (3, (16, 8, 16), 0.5, 2)])
+def test_step_observed_matches_oracle(lib, grid):
+    """Per-step logged (N, F_z, E) of R(dt/2) psi(t_i) against the oracle, and
+    the stepped field against plain spin1_step."""
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    p, dt, n = oparams(P1), 0.02, 6
+    psi0 = random_field(14, og.shape, noise=0.5)
+    ref, cur = [], psi0
+    for i in range(n):
+        ref.append(O.observables(O.local_flow(cur, 0.5 * dt, p.c0, p.c1), p, og))
+        cur = O.strang_step(cur, dt, p, og)
+    ref = np.array(ref)
+    for dtype, tol in (("c128", 1e-12), ("c64", 2e-6)):
+        sim = run_gpu(lib, grid, P1, dtype, psi0=psi0)
+        obs = sim.step_observed(n, dt)
+        assert obs.shape == (n, og.samples, 3)
+        assert np.allclose(obs, ref, rtol=tol, atol=tol * np.abs(ref).max()), dtype
+        plain = run_gpu(lib, grid, P1, dtype, psi0=psi0, nsteps=n, dt=dt).fields()[0]
+        assert rel(sim.fields()[0], plain) < (1e-13 if dtype == "c128" else 1e-6), dtype
+        # N and F_z are those of psi(t_i) itself (R conserves them)
+        assert np.allclose(obs[0, :, :2], O.observables(psi0, p, og)[:, :2], rtol=tol)
+
+
+def test_step_observed_groups_and_errors(lib):
+    grids = [(2, (32, 32), 0.5, 2), (1, (128,), 0.5, 3)]
+    sim = lib.Sim(grids, P1, dtype="c128")
+    sim.init_wigner(15)
+    f0 = sim.fields()
+    obs = sim.step_observed(4, 0.02, group=1)
+    assert obs.shape == (4, 3, 3)
+    f = sim.fields()
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        assert rel(f[gi], O.evolve(f0[gi], 4, 0.02, oparams(P1), og)) < 1e-12
+    import torch
+    buf = torch.zeros(64, dtype=torch.float64, device=sim.device)
+    with pytest.raises(lib.Spin1Error):
+        lib.step_observed(sim.ctx, 2, 0.02, 2, buf.data_ptr())  # no group 2
+    with pytest.raises(lib.Spin1Error):
+        lib.step_observed(sim.ctx, 2, 0.02, 0, 0)  # NULL log
+    assert sim.step_observed(0, 0.02).shape == (0, 2, 3)
+
+
 def test_norm_and_fz_conserved_on_gpu(lib):
     grid = (2, (128, 128), 0.5, 4)
     sim = run_gpu(lib, grid, P1, "c64", seed=21)
