@@ -199,8 +199,18 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   (range 1..1024); 1 = one x-pass launch per step, as for 2D/3D groups;
  *   0 (default) = automatic: 64 for Nx <= 1024, 1 above (where a sample's
  *   three components no longer fit one workgroup's registers).  The result
- *   is the same map either way (same arithmetic, different kernel). */
-enum spin1_option { SPIN1_OPT_GRAPHS = 0, SPIN1_OPT_GRAPH_MAX_STEPS = 1, SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2 };
+ *   is the same map either way (same arithmetic, different kernel).
+ * SPIN1_OPT_GROUPED_X: 1 (default) = when two or more bound groups are
+ *   stepped one x-pass launch per step and have Nx in 16..1024 (FP32) or
+ *   16..512 (FP64), their x-passes run as one persistent launch per step
+ *   (radix 8, groups back to back in one work list); 0 = one x-pass launch
+ *   per group.  Same arithmetic either way. */
+enum spin1_option {
+  SPIN1_OPT_GRAPHS = 0,
+  SPIN1_OPT_GRAPH_MAX_STEPS = 1,
+  SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2,
+  SPIN1_OPT_GROUPED_X = 3
+};
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 
 /* Kernel kinds reported by the profiling hooks. */

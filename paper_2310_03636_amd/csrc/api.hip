@@ -215,6 +215,7 @@ struct spin1_ctx {
   bool use_graphs = true;
   int64_t graph_max_steps = 1024;
   int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
+  bool grouped_x = true;
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -359,18 +360,9 @@ int log2_of(int n) {
 
 int variant_of(spin1_ctx* ctx, int pass, int n) { return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)]; }
 
-int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double dt, double tau_open,
-                       double tau_close) {
-  XPassArgs xa = xargs(ctx, G);
-  xa.psi = field;
-  xa.tau_pre = tau_open;
-  xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
+// the passes of a step after the x-pass: y/z passes, closing half step (2D/3D)
+int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double tau_close) {
   hipError_t e;
-  {
-    Prof pr(ctx, SPIN1_K_XPASS);
-    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, variant_of(ctx, 0, G.geo.n[0]));
-  }
-  if (e != hipSuccess) return hip_fail(e, "x-pass");
   for (int a = 1; a < G.geo.dim; ++a) {
     const SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
     {
@@ -387,6 +379,22 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
     if (e != hipSuccess) return hip_fail(e, "closing local update");
   }
   return SPIN1_OK;
+}
+
+int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double dt, double tau_open,
+                       double tau_close) {
+  (void)dt;
+  XPassArgs xa = xargs(ctx, G);
+  xa.psi = field;
+  xa.tau_pre = tau_open;
+  xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
+  hipError_t e;
+  {
+    Prof pr(ctx, SPIN1_K_XPASS);
+    e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, variant_of(ctx, 0, G.geo.n[0]));
+  }
+  if (e != hipSuccess) return hip_fail(e, "x-pass");
+  return enqueue_group_rest(ctx, G, field, tau_close);
 }
 
 // 1D groups with more than one step per launch: consecutive chunks of up to
@@ -415,17 +423,72 @@ int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double d
   return SPIN1_OK;
 }
 
+// Groups whose step x-passes share one grouped launch: stepped one launch
+// per step, pencil lengths the grouped kernel takes; at least two of them.
+std::vector<size_t> grouped_x_set(const spin1_ctx* ctx) {
+  std::vector<size_t> out;
+  if (!ctx->grouped_x) return out;
+  for (size_t g = 0; g < ctx->groups.size() && out.size() < size_t(kMaxGroupedX); ++g) {
+    const GroupState& G = ctx->groups[g];
+    if (!multi_1d(ctx, G) && G.geo.n[0] >= 16 && G.geo.n[0] <= grouped_x_max_n(ctx->dbl)) out.push_back(g);
+  }
+  if (out.size() < 2) out.clear();
+  return out;
+}
+
+int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau_open, double tau_close) {
+  XGroupArgs ga{};
+  int64_t items = 0;
+  for (size_t j = 0; j < set.size(); ++j) {
+    const GroupState& G = ctx->groups[set[j]];
+    XGroupEntry& e = ga.g[j];
+    e.psi = G.psi;
+    e.tw = at(ctx, G.lay.tw[0]);
+    e.ph = at(ctx, G.lay.ph[0]);
+    e.rows = G.geo.rows;
+    e.sites = G.geo.sites;
+    e.pencils = int64_t(G.geo.S) * G.geo.rows;
+    e.item_begin = items;
+    e.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
+    e.n = G.geo.n[0];
+    e.lg_rows = log2_of(int(G.geo.rows));
+    items += grouped_x_items(e.n, e.pencils);
+  }
+  ga.item_end = items;
+  ga.ngroups = int(set.size());
+  ga.tau_pre = tau_open;
+  ga.c0 = ctx->p.c0;
+  ga.c1 = ctx->p.c1;
+  hipError_t e;
+  {
+    Prof pr(ctx, SPIN1_K_XPASS);
+    e = launch_xpass_grouped(ctx->stream, ctx->dbl, ga);
+  }
+  if (e != hipSuccess) return hip_fail(e, "grouped x-pass");
+  return SPIN1_OK;
+}
+
 int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
   for (auto& G : ctx->groups)
     if (multi_1d(ctx, G)) {
       const int rc = enqueue_group_multi(ctx, G, n, dt);
       if (rc) return rc;
     }
+  const std::vector<size_t> set = grouped_x_set(ctx);
+  std::vector<char> in_set(ctx->groups.size(), 0);
+  for (size_t g : set) in_set[g] = 1;
   for (int64_t i = 0; i < n; ++i) {
     const double pre = i == 0 ? 0.5 * dt : dt;
     const double close = i == n - 1 ? 0.5 * dt : 0.0;
-    for (auto& G : ctx->groups) {
-      if (multi_1d(ctx, G)) continue;
+    if (!set.empty()) {
+      int rc = enqueue_grouped_x(ctx, set, pre, close);
+      for (size_t g : set)
+        if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close);
+      if (rc) return rc;
+    }
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
+      const GroupState& G = ctx->groups[g];
+      if (multi_1d(ctx, G) || in_set[g]) continue;
       const int rc = enqueue_group_step(ctx, G, G.psi, dt, pre, close);
       if (rc) return rc;
     }
@@ -1015,6 +1078,10 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
     case SPIN1_OPT_GRAPH_MAX_STEPS:
       if (value < 1) return fail(SPIN1_EINVAL, "graph step limit must be >= 1");
       ctx->graph_max_steps = value;
+      return SPIN1_OK;
+    case SPIN1_OPT_GROUPED_X:
+      ctx->grouped_x = value != 0;
+      ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_STEPS_PER_LAUNCH_1D:
       if (value < 0 || value > 1024) return fail(SPIN1_EINVAL, "1D steps per launch must be in 0..1024");

@@ -41,6 +41,26 @@ struct XPassArgs {
   int lg_rows;      // log2(rows), set by the launcher
 };
 
+// One x-pass launch over the step passes of several groups (pencil lengths
+// 16..kGroupedMaxN, radix 8, 256 threads per workgroup).  Group g owns the
+// work items [item_begin[g], item_begin[g + 1]) of P_g = 2048 / n_g pencils each.
+constexpr int kMaxGroupedX = 8;
+struct XGroupEntry {
+  void* psi;
+  const void* tw;
+  const void* ph;
+  int64_t rows, sites, pencils;  // pencils = S * rows
+  int64_t item_begin;
+  double tau_post;
+  int n, lg_rows;
+};
+struct XGroupArgs {
+  XGroupEntry g[kMaxGroupedX];
+  int64_t item_end;  // item_begin of a virtual group past the last
+  int ngroups;
+  double tau_pre, c0, c1;
+};
+
 struct SPassArgs {
   void* psi;        // field base
   void* out;        // SF_POWER: real power array, same layout as psi (1 component)
@@ -66,6 +86,11 @@ hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint6
 hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant = 0);
 hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant = 0);
 int step_variants();
+// largest pencil length the grouped x-pass takes
+int grouped_x_max_n(bool dbl);
+// work items of a group in the grouped x-pass
+int64_t grouped_x_items(int n, int64_t pencils);
+hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a);
 // 1D: K split steps of one pencil per workgroup in one launch (open_half: the
 // first step opens with R(dt/2) instead of R(dt); close_half: closing R(dt/2))
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,

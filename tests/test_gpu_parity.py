@@ -239,6 +239,29 @@ def test_uneven_groups_step(lib):
         assert rel(f[gi], ref) < 1e-11
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_grouped_x_pass_matches_oracle(lib, dtype, tol):
+    """Groups of different pencil lengths share one x-pass launch per step
+    (a 1D group stepped one launch per step among them, with its closing half
+    step); results equal the oracle and the per-group launches."""
+    grids = [(2, (64, 32), 0.5, 2), (1, (256,), 0.5, 3), (3, (16, 16, 8), 0.5, 1), (2, (1024, 16), 0.5, 1),
+             (2, (16, 64), 0.5, 3)]
+    out = {}
+    for grouped in (1, 0):
+        sim = lib.Sim(grids, P1, dtype=dtype)
+        sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 1)
+        sim.set_option(lib.OPT_GROUPED_X, grouped)
+        sim.init_wigner(16)
+        sim.step(7, 0.02)
+        sim.step(3, 0.02)
+        out[grouped] = sim.fields()
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        ref = O.evolve(O.init_wigner(16, og, oparams(P1), group=gi), 10, 0.02, oparams(P1), og)
+        assert rel(out[1][gi], ref) < tol, gi
+        assert rel(out[1][gi], out[0][gi]) < tol / 10, gi
+
+
 # ------------------------------------------------------------------ structure factor
 @pytest.mark.parametrize("grid", [(1, (256,), 0.5, 4), (2, (32, 64), 0.5, 3), (3, (16, 16, 8), 0.5, 2),
                                   (1, (4096,), 0.5, 2), (2, (256, 256), 0.5, 1)])
