@@ -204,13 +204,24 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   stepped one x-pass launch per step and have Nx in 16..1024 (FP32) or
  *   16..512 (FP64), their x-passes run as one persistent launch per step
  *   (radix 8, groups back to back in one work list); 0 = one x-pass launch
- *   per group.  Same arithmetic either way. */
+ *   per group.  Same arithmetic either way.
+ * SPIN1_OPT_SCHEME: SPIN1_SCHEME_STRANG (default), the symmetric split with
+ *   the exact local flow described at spin1_step; or SPIN1_SCHEME_PAPER, the
+ *   paper's own scheme in its order (Sec. 2.2): per step the kinetic phase of
+ *   Eq. (3) (without q), then the diagonal phases of Eq. (4) (q and the
+ *   density terms, densities of the field they act on), then the mixing of
+ *   Eq. (5) with couplings averaged over the field and a one-step predictor.
+ *   First order in dt; it converges to the same flow as dt -> 0.  Reverse
+ *   mode and spin1_step_observed take the Strang scheme only
+ *   (SPIN1_EUNSUPPORTED otherwise). */
 enum spin1_option {
   SPIN1_OPT_GRAPHS = 0,
   SPIN1_OPT_GRAPH_MAX_STEPS = 1,
   SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2,
-  SPIN1_OPT_GROUPED_X = 3
+  SPIN1_OPT_GROUPED_X = 3,
+  SPIN1_OPT_SCHEME = 4
 };
+enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 
 /* Kernel kinds reported by the profiling hooks. */

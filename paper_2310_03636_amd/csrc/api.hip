@@ -216,6 +216,7 @@ struct spin1_ctx {
   int64_t graph_max_steps = 1024;
   int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
   bool grouped_x = true;
+  int scheme = SPIN1_SCHEME_STRANG;
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -468,7 +469,37 @@ int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau
   return SPIN1_OK;
 }
 
+// The paper's Lie scheme, psi <- O D K psi per step (K without q): the D, O
+// of step i run in the x-pass prologue of step i + 1 (2D/3D) or in the
+// x-pass epilogue (1D); after the last step a local pass applies them.
+int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
+  for (int64_t i = 0; i < n; ++i)
+    for (auto& G : ctx->groups) {
+      XPassArgs xa = xargs(ctx, G);
+      xa.tau_pre = G.geo.dim > 1 && i > 0 ? dt : 0.0;
+      xa.tau_post = G.geo.dim == 1 ? dt : 0.0;
+      hipError_t e;
+      {
+        Prof pr(ctx, SPIN1_K_XPASS);
+        e = launch_xpass(ctx->stream, ctx->dbl, MODE_PAPER, G.geo.n[0], xa);
+      }
+      if (e != hipSuccess) return hip_fail(e, "Lie-scheme x-pass");
+      const int rc = enqueue_group_rest(ctx, G, G.psi, 0.0);
+      if (rc) return rc;
+      if (G.geo.dim > 1 && i == n - 1) {
+        {
+          Prof pr(ctx, SPIN1_K_LOCAL);
+          e = launch_paper_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, dt, ctx->p.c0, ctx->p.c1,
+                                 ctx->p.q);
+        }
+        if (e != hipSuccess) return hip_fail(e, "Lie-scheme local pass");
+      }
+    }
+  return SPIN1_OK;
+}
+
 int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
+  if (ctx->scheme == SPIN1_SCHEME_PAPER) return enqueue_steps_paper(ctx, n, dt);
   for (auto& G : ctx->groups)
     if (multi_1d(ctx, G)) {
       const int rc = enqueue_group_multi(ctx, G, n, dt);
@@ -810,6 +841,7 @@ int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, dou
   if (rc) return rc;
   if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
   if (!obs_dev) return fail(SPIN1_EINVAL, "obs_dev is NULL");
+  if (ctx->scheme != SPIN1_SCHEME_STRANG) return fail(SPIN1_EUNSUPPORTED, "the step log takes the Strang scheme");
   if (n < 0) return fail(SPIN1_EINVAL, "n must be >= 0");
   if (!isfinite(dt)) return fail(SPIN1_EINVAL, "dt must be finite");
   if (n == 0) return SPIN1_OK;
@@ -861,6 +893,7 @@ static int check_adjoint_args(spin1_ctx* ctx, int64_t n, double dt, int64_t ever
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
   if (ctx->groups.size() != 1) return fail(SPIN1_EUNSUPPORTED, "reverse mode supports one bound group");
+  if (ctx->scheme != SPIN1_SCHEME_STRANG) return fail(SPIN1_EUNSUPPORTED, "reverse mode takes the Strang scheme");
   if (n < 1) return fail(SPIN1_EINVAL, "n must be >= 1");
   if (every < 1) return fail(SPIN1_EINVAL, "checkpoint interval must be >= 1");
   if (!isfinite(dt) || dt == 0.0) return fail(SPIN1_EINVAL, "dt must be finite and nonzero");
@@ -1078,6 +1111,11 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
     case SPIN1_OPT_GRAPH_MAX_STEPS:
       if (value < 1) return fail(SPIN1_EINVAL, "graph step limit must be >= 1");
       ctx->graph_max_steps = value;
+      return SPIN1_OK;
+    case SPIN1_OPT_SCHEME:
+      if (value != SPIN1_SCHEME_STRANG && value != SPIN1_SCHEME_PAPER) return fail(SPIN1_EINVAL, "unknown scheme");
+      ctx->scheme = int(value);
+      ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_GROUPED_X:
       ctx->grouped_x = value != 0;

@@ -459,6 +459,56 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
 }
 
 // ---------------------------------------------------------------------------
+// The paper's own local sub-steps over dt, in its order (Lie scheme, Sec. 2.2):
+//  (4) diagonal phases exp(-i f_m dt) with f_{+1} = q + (c0 + c1) n - 2 c1 |psi_-1|^2,
+//      f_0 = (c0 + c1) n - c1 |psi_0|^2, f_{-1} = q + (c0 + c1) n - 2 c1 |psi_1|^2,
+//      densities of the field they act on;
+//  (5) off-diagonal mixing exp(-i theta S(a, b)), theta = c1 dt, with
+//      S(a, b) = [[0, a, 0], [a*, 0, b], [0, b*, 0]] and the couplings averaged
+//      over the field and a predictor: a0 = psi_-1* psi_0, b0 = psi_0* psi_1,
+//      tpsi = psi - i theta S(a0, b0) psi, a = (a0 + tpsi_-1* tpsi_0)/2,
+//      b = (b0 + tpsi_0* tpsi_1)/2.  With lambda^2 = |a|^2 + |b|^2 and
+//      S^3 = lambda^2 S the exponential is 1 - i s S + c S^2, s = sin(x)/lambda,
+//      c = (cos x - 1)/lambda^2, x = lambda theta (same coefficients as the
+//      exact rotation, from the half-angle sinc).
+// ---------------------------------------------------------------------------
+template <typename Real>
+__device__ __forceinline__ void paper_local_update(Cx<Real>* psi, Real dt, Real c0, Real c1, Real q) {
+  const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
+  const Real n = d1 + d0 + dm;
+  const Real base = (c0 + c1) * n;
+  const Real f[3] = {q + base - Real(2) * c1 * dm, base - c1 * d0, q + base - Real(2) * c1 * d1};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    Real sn, cs;
+    angle_sincos(f[m] * dt, &sn, &cs);
+    psi[m] = psi[m] * Cx<Real>{cs, -sn};
+  }
+  const Real theta = c1 * dt;
+  // S(a, b) v
+  auto apply_S = [](Cx<Real> a, Cx<Real> b, const Cx<Real>* v, Cx<Real>* out) {
+    out[0] = a * v[1];
+    out[1] = cmulc(a, v[0]) + b * v[2];
+    out[2] = cmulc(b, v[1]);
+  };
+  const Cx<Real> a0 = cmulc(psi[2], psi[1]), b0 = cmulc(psi[1], psi[0]);
+  Cx<Real> sv[3], tp[3];
+  apply_S(a0, b0, psi, sv);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) tp[m] = {psi[m].re + theta * sv[m].im, psi[m].im - theta * sv[m].re};
+  const Cx<Real> a = scale(a0 + cmulc(tp[2], tp[1]), Real(0.5));
+  const Cx<Real> b = scale(b0 + cmulc(tp[1], tp[0]), Real(0.5));
+  Real s, c;
+  rotation_coeffs(norm2(a) + norm2(b), theta, &s, &c);
+  Cx<Real> s1[3], s2[3];
+  apply_S(a, b, psi, s1);
+  apply_S(a, b, s1, s2);
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    psi[m] = {psi[m].re + s * s1[m].im + c * s2[m].re, psi[m].im - s * s1[m].re + c * s2[m].im};
+}
+
+// ---------------------------------------------------------------------------
 // Vector-Jacobian product of the local update (reverse mode).  Gradients use
 // the real convention G = dL/dRe + i dL/dIm, so dL = Re<G, dpsi> with
 // <a, b> = sum conj(a) b.  For psi' = exp(-i c0 n tau) U psi with

@@ -24,7 +24,9 @@ int spass_tx(int n, bool dbl);
 // Kernel modes
 // MODE_STEP_LOG: a step pass that also writes the FP64 partial sums of
 // MODE_MEASURE for the state its kinetic sub-step starts from
-enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3, MODE_STEP_LOG = 4 };
+// MODE_PAPER: x-pass of the paper's Lie scheme: [D, O of the previous step
+// (tau_pre = dt)] K_x(dt) without q [D, O (tau_post = dt, 1D)]
+enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3, MODE_STEP_LOG = 4, MODE_PAPER = 5 };
 
 struct XPassArgs {
   void* psi;        // field base [S][3][rows][Nx] (STEP, MEASURE, SF*)
@@ -96,6 +98,9 @@ hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a);
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
                             bool close_half);
 hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
+// the paper's local sub-steps (4)-(5) over dt at every site
+hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double dt, double c0,
+                              double c1, double q);
 hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
                       const int32_t* offs, int nbins, double* out);
 hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,

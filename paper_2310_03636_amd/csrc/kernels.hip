@@ -301,6 +301,30 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
         for (int e = 0; e < R; ++e) base[m * a.sites + e * T] = v[m][e];
     }
     if constexpr (MODE == MODE_STEP_LOG) pencil_sums_out<T>(acc, lds, p, t, active, a.part + pid * 4);
+  } else if constexpr (MODE == MODE_PAPER) {
+    const Real c0 = Real(a.c0), c1 = Real(a.c1), q = Real(a.q);
+    auto local_all = [&](Real dt) {
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        paper_local_update(site, dt, c0, c1, q);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    };
+    if (a.tau_pre != 0.0) local_all(Real(a.tau_pre));
+    // kinetic phase alone (the m = 0 row of the x table; q sits in D)
+    const TabEntry<Real>* ph0 = static_cast<const TabEntry<Real>*>(a.ph) + N;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph0);
+    if (a.tau_post != 0.0) local_all(Real(a.tau_post));
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int e = 0; e < R; ++e) base[m * a.sites + e * T] = v[m][e];
+    }
   } else if constexpr (MODE == MODE_MEASURE) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -815,6 +839,21 @@ __global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sit
   }
 }
 
+template <typename Real>
+__global__ __launch_bounds__(256) void k_paper_local(Cx<Real>* psi, int S, int64_t sites, Real dt, Real c0, Real c1,
+                                                     Real q) {
+  const int64_t total = int64_t(S) * sites;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    Cx<Real>* b = psi + s * 3 * sites + x;
+    Cx<Real> site[3] = {b[0], b[sites], b[2 * sites]};
+    paper_local_update(site, dt, c0, c1, q);
+    b[0] = site[0];
+    b[sites] = site[1];
+    b[2 * sites] = site[2];
+  }
+}
+
 // --------------------------------------------------------------------------
 // phase and twiddle tables, computed in FP64 (hi + lo floats in single precision)
 // ph[m][k] = exp(-i (k^2/2 + q m^2) dt) / N (m = +1, 0, -1 when ncomp = 3)
@@ -1170,6 +1209,7 @@ static hipError_t xpass_t(hipStream_t st, int mode, int n, const XPassArgs& a, i
     case MODE_SF: return xpass_mode<Real, MODE_SF>(st, n, a, v);
     case MODE_SF_POWER: return xpass_mode<Real, MODE_SF_POWER>(st, n, a, v);
     case MODE_STEP_LOG: return xpass_mode<Real, MODE_STEP_LOG>(st, n, a, v);
+    case MODE_PAPER: return xpass_mode<Real, MODE_PAPER>(st, n, a, v);
   }
   return hipErrorInvalidValue;
 }
@@ -1338,6 +1378,18 @@ hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t site
   else
     hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
                        float(tau), float(c0), float(c1));
+  return hipGetLastError();
+}
+
+hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double dt, double c0,
+                              double c1, double q) {
+  const unsigned blocks = grid_for(int64_t(S) * sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_paper_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites,
+                       dt, c0, c1, q);
+  else
+    hipLaunchKernelGGL(k_paper_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
+                       float(dt), float(c0), float(c1), float(q));
   return hipGetLastError();
 }
 

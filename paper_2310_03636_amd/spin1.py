@@ -29,7 +29,8 @@ FUNCTIONS = [
     "spin1_num_variants", "spin1_autotune", "spin1_get_variant", "spin1_set_variant", "spin1_last_error",
 ]
 
-OPT_GRAPHS, OPT_GRAPH_MAX_STEPS, OPT_STEPS_PER_LAUNCH_1D, OPT_GROUPED_X = 0, 1, 2, 3
+OPT_GRAPHS, OPT_GRAPH_MAX_STEPS, OPT_STEPS_PER_LAUNCH_1D, OPT_GROUPED_X, OPT_SCHEME = 0, 1, 2, 3, 4
+SCHEME_STRANG, SCHEME_PAPER = 0, 1
 
 KERNEL_KINDS = ["xpass", "ypass", "zpass", "local", "spectrum", "shells", "observables", "other"]
 

@@ -262,6 +262,54 @@ def test_grouped_x_pass_matches_oracle(lib, dtype, tol):
         assert rel(out[1][gi], out[0][gi]) < tol / 10, gi
 
 
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 3), (2, (64, 32), 0.5, 2), (3, (16, 8, 16), 0.5, 2)])
+def test_paper_scheme_matches_oracle(lib, grid):
+    """The paper's Lie scheme (kinetic, Eq. (4) phases, Eq. (5) mixing with the
+    predictor) against the oracle's literal step, split over two calls."""
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    p, dt = oparams(P1), 0.02
+    psi0 = random_field(17, og.shape, noise=0.5)
+    ref = psi0
+    for _ in range(7):
+        ref = O.paper_step(ref, dt, p, og)
+    for dtype, tol in (("c128", 1e-12), ("c64", 2e-5)):
+        sim = lib.Sim([grid], P1, dtype=dtype)
+        sim.set_option(lib.OPT_SCHEME, lib.SCHEME_PAPER)
+        sim.set_fields([psi0])
+        sim.step(4, dt)
+        sim.step(3, dt)
+        assert rel(sim.fields()[0], ref) < tol, dtype
+
+
+def test_paper_scheme_first_order_and_limits(lib):
+    """First-order convergence to the same flow as the symmetric split, on the
+    GPU; the scheme is rejected where only the symmetric split is supported."""
+    grid = (2, (32, 32), 0.5, 2)
+    og = O.Grid(2, (32, 32), 0.5, 2)
+    psi0 = random_field(18, og.shape, noise=0.3)
+    t_end = 0.32
+
+    def run(scheme, m):
+        sim = lib.Sim([grid], P1, dtype="c128")
+        sim.set_option(lib.OPT_SCHEME, scheme)
+        sim.set_fields([psi0])
+        sim.step(m, t_end / m)
+        return sim.fields()[0]
+
+    ref = run(lib.SCHEME_STRANG, 256)
+    e = [rel(run(lib.SCHEME_PAPER, m), ref) for m in (16, 32, 64)]
+    assert 1.7 < e[0] / e[1] < 2.3 and 1.7 < e[1] / e[2] < 2.3, e
+    sim = lib.Sim([grid], P1, dtype="c128")
+    sim.init_wigner(3)
+    sim.set_option(lib.OPT_SCHEME, lib.SCHEME_PAPER)
+    with pytest.raises(lib.Spin1Error):
+        sim.step_observed(2, 0.02)
+    with pytest.raises(lib.Spin1Error):
+        sim.forward_ckpt(4, 0.02, 2)
+    with pytest.raises(lib.Spin1Error):
+        sim.set_option(lib.OPT_SCHEME, 7)
+
+
 # ------------------------------------------------------------------ structure factor
 @pytest.mark.parametrize("grid", [(1, (256,), 0.5, 4), (2, (32, 64), 0.5, 3), (3, (16, 16, 8), 0.5, 2),
                                   (1, (4096,), 0.5, 2), (2, (256, 256), 0.5, 1)])
