@@ -295,7 +295,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the Wigner samples are independent, so N GPUs would each run "
-              "this same single-GPU workload on their own share (see DESIGN.md); --gpus %d is not run."
+              "this same single-GPU workload on their own share; --gpus %d is not run."
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -5,7 +5,7 @@ direct: every step is written out in the order the method states it, with
 library primitives (``numpy.linalg.eigh``, the own FFT of ``oracle.fft``)
 as building blocks and no blocking, fusion or merging of sub-steps.
 
-Conventions (readings of the paper; each is listed in the design doc):
+Conventions (readings of the paper where it is silent or ambiguous):
   * hbar = m = 1 (the kinetic phase of Eq. (3) is exp(-i dt |k|^2 / 2)).
   * Components are ordered (psi_{+1}, psi_0, psi_{-1}) as in Eq. (2);
     array axis 1 holds them, index c = 0, 1, 2 <-> m = +1, 0, -1.

@@ -1057,8 +1057,8 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
       const int pass = axis == 0 ? 0 : 1;
       const int lg = log2_of(G.geo.n[axis]);
       seen[pass][lg] = true;
-      // round 0 brings the clocks up and is not counted; round 1 is timed
-      for (int round = 0; round < 2 && !rc; ++round)
+      // sweep 0 brings the clocks up and is not counted; sweep 1 is timed
+      for (int sweep = 0; sweep < 2 && !rc; ++sweep)
       for (int v = 0; v < nv && !rc; ++v) {
         auto launch = [&]() {
           if (pass == 0) {
@@ -1081,7 +1081,7 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
           rc = hip_fail(e, "autotune timing");
           break;
         }
-        if (round == 1) total[pass][lg][v] += double(ms);
+        if (sweep == 1) total[pass][lg][v] += double(ms);
       }
     }
     if (rc) break;
