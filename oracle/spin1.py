@@ -102,6 +102,46 @@ def f_perp(psi):
     return fx + 1j * fy
 
 
+def spin_texture(psi, grid):
+    """Real-space transverse-spin diagnostics per sample, array [S, 3]:
+    (mean |F_perp|, mean |F_perp|^2, Q_w), means over the lattice sites.
+
+    F_perp = |F_perp| exp(i phi_L) (Fig. 1 caption, Sec. 2.1).  Q_w is the
+    winding of the Larmor phase along x, the lattice form of the integral of
+    d phi_L / dx over the periodic line in units of 2 pi: the phase steps
+    phi_L(x_{j+1}) - phi_L(x_j), each taken in [-pi, pi), summed around every
+    x-row and over the rows (in 1D, the paper's Q_w).  phi_L = 0 where
+    F_perp = 0.
+    """
+    fp = f_perp(psi)
+    axes = tuple(range(1, 1 + grid.dim))
+    mag = np.abs(fp)
+    phi = np.angle(fp)
+    step = np.roll(phi, -1, axis=-1) - phi
+    step = step - 2.0 * np.pi * np.floor((step + np.pi) / (2.0 * np.pi))
+    out = np.empty((grid.samples, 3))
+    out[:, 0] = np.mean(mag, axis=axes)
+    out[:, 1] = np.mean(mag ** 2, axis=axes)
+    out[:, 2] = np.sum(step, axis=axes) / (2.0 * np.pi)
+    return out
+
+
+def spin_helix(grid, winding, n0=1.0):
+    """Transversely polarised state whose spin turns `winding` times along x:
+    the spin-1 state of spin n0 along (cos phi, sin phi, 0) with
+    phi = 2 pi winding x / L, i.e. psi = sqrt(n0) (e^{-i phi}/2, 1/sqrt2, e^{i phi}/2);
+    F_perp = n0 e^{i phi}.  Array [S, 3, spatial]."""
+    nx = grid.n[0]
+    phi = 2.0 * np.pi * winding * np.arange(nx) / nx
+    shape = grid.spatial
+    phi = np.broadcast_to(phi, shape)
+    psi = np.empty((grid.samples, 3) + shape, dtype=np.complex128)
+    psi[:, 0] = 0.5 * np.exp(-1j * phi)
+    psi[:, 1] = 1.0 / np.sqrt(2.0)
+    psi[:, 2] = 0.5 * np.exp(1j * phi)
+    return np.sqrt(n0) * psi
+
+
 # --------------------------------------------------------------------------
 # lattice and momentum grid (Eq. (3), Laplacian of Sec. 2.2)
 # --------------------------------------------------------------------------

@@ -450,3 +450,48 @@ def test_observables_uniform_closed_form():
     assert abs(o[1] - fz * vol) < 1e-13
     e = 0.5 * p.c0 * n * n + 0.5 * p.c1 * (abs(fp) ** 2 + fz ** 2) + p.q * (abs(v[0]) ** 2 + abs(v[2]) ** 2)
     assert abs(o[2] - e * vol) < 1e-13
+
+
+# ------------------------------------------------------------------ real-space spin texture (Fig. 1)
+@pytest.mark.parametrize("dim,n", [(1, (64,)), (2, (32, 8)), (3, (16, 4, 2))])
+@pytest.mark.parametrize("w", [-3, 0, 1, 5])
+def test_spin_texture_of_helix_is_integer_winding(dim, n, w):
+    """A helix turning w times along x has F_perp = n0 e^{i phi} (|F_perp| = n0)
+    and winds w times on every x-row."""
+    g = O.Grid(dim, n, 0.5, 2)
+    psi = O.spin_helix(g, w, n0=1.7)
+    fp = O.f_perp(psi)
+    phi = 2 * np.pi * w * np.arange(n[0]) / n[0]
+    assert np.allclose(fp, 1.7 * np.exp(1j * phi), atol=1e-14)
+    tex = O.spin_texture(psi, g)
+    rows = g.sites // n[0]
+    assert np.allclose(tex[:, 0], 1.7, rtol=1e-14)
+    assert np.allclose(tex[:, 1], 1.7 ** 2, rtol=1e-14)
+    assert np.allclose(tex[:, 2], w * rows, atol=1e-12)
+
+
+def test_spin_texture_winding_by_hand():
+    """Four sites with Larmor phases 0, pi/2, pi, 3pi/2 wind once; the
+    reversed order winds -1; a jump by more than pi counts the short way."""
+    g = O.Grid(1, (4,), 1.0, 1)
+    for phases, expect in (([0, 0.5, 1.0, 1.5], 1), ([0, 1.5, 1.0, 0.5], -1), ([0, 1.2, 1.2, 1.2], 0)):
+        fp = np.exp(1j * np.pi * np.array(phases))
+        # a transversely polarised spinor per site with this F_perp
+        psi = np.empty((1, 3, 4), dtype=np.complex128)
+        psi[0, 0] = 0.5 * np.conj(fp)
+        psi[0, 1] = 1 / np.sqrt(2)
+        psi[0, 2] = 0.5 * fp
+        assert abs(O.spin_texture(psi, g)[0, 2] - expect) < 1e-12
+
+
+def test_spin_texture_invariances_and_parseval():
+    """A spin rotation about z moves phi_L uniformly (Q_w and |F_perp| fixed);
+    the mean |F_perp|^2 equals the shell sum of S(k) (Parseval)."""
+    g = O.Grid(2, (16, 8), 0.5, 3)
+    psi = random_field(41, g.shape, noise=0.6)
+    tex = O.spin_texture(psi, g)
+    alpha = 0.77
+    rot = psi * np.exp(-1j * alpha * np.array([1.0, 0.0, -1.0]))[None, :, None, None]
+    assert np.allclose(O.spin_texture(rot, g), tex, atol=1e-12)
+    bins = O.structure_factor(psi, g)
+    assert np.allclose((bins * O.bin_counts(g)).sum(1) / g.sites, tex[:, 1], rtol=1e-12)
