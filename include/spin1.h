@@ -134,6 +134,21 @@ SPIN1_API int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins
  * E the energy whose Wirtinger derivative is the right-hand side of Eq. (2). */
 SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
 
+/* Transverse spin F_perp = F_x + i F_y = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1)
+ * of group `group` at every site (Sec. 2.1 and Fig. 1: spin length |F_perp|
+ * and Larmor phase phi_L = arg F_perp): fperp_dev is a device array
+ * [S][Nz][Ny][Nx] of complex values in the field's precision. */
+SPIN1_API int spin1_transverse_spin(spin1_ctx* ctx, int32_t group, void* fperp_dev);
+
+/* Real-space spin texture of group `group` (Fig. 1): out_dev is a device
+ * array [S][3] of double holding, per sample, the site means of |F_perp| and
+ * |F_perp|^2 and the winding Q_w of the Larmor phase along x: the phase steps
+ * phi_L(x_{j+1}) - phi_L(x_j), each taken in [-pi, pi) (phi_L = 0 where
+ * F_perp = 0), summed around every periodic x-row and over the rows, divided
+ * by 2 pi (in 1D the paper's winding number; an integer up to rounding).
+ * Sums in FP64, fixed order. */
+SPIN1_API int spin1_spin_texture(spin1_ctx* ctx, int32_t group, double* out_dev);
+
 /* spin1_step(n, dt) that also logs, for group `group`, the FP64 (N, F_z, E)
  * of every step: obs_dev is a device array [n][S][3] of double, row i being
  * the observables of R(dt/2) psi(t + i dt), the state the kinetic sub-step of

@@ -795,6 +795,32 @@ int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
   return SPIN1_OK;
 }
 
+int spin1_transverse_spin(spin1_ctx* ctx, int32_t group, void* fperp_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!fperp_dev) return fail(SPIN1_EINVAL, "fperp_dev is NULL");
+  const GroupState& G = ctx->groups[size_t(group)];
+  Prof pr(ctx, SPIN1_K_OBSERVABLES);
+  const hipError_t e = launch_f_perp(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, fperp_dev);
+  if (e != hipSuccess) return hip_fail(e, "transverse spin");
+  return SPIN1_OK;
+}
+
+int spin1_spin_texture(spin1_ctx* ctx, int32_t group, double* out_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!out_dev) return fail(SPIN1_EINVAL, "out_dev is NULL");
+  const GroupState& G = ctx->groups[size_t(group)];
+  Prof pr(ctx, SPIN1_K_OBSERVABLES);
+  // the x-pass partials ([S*rows][4] doubles) hold the [S*rows][3] row sums
+  const hipError_t e = launch_texture(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.rows, G.geo.sites, G.geo.n[0],
+                                      reinterpret_cast<double*>(at(ctx, G.lay.part[0])), out_dev);
+  if (e != hipSuccess) return hip_fail(e, "spin texture");
+  return SPIN1_OK;
+}
+
 // One step of group G with the observables of the state its kinetic sub-step
 // starts from summed inside the passes and finished into obs (S x 3).
 static int enqueue_group_step_logged(spin1_ctx* ctx, const GroupState& G, double dt, double tau_open,

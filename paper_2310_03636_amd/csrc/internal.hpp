@@ -98,6 +98,11 @@ hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a);
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
                             bool close_half);
 hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
+// F_perp per site [S][sites] (field precision)
+hipError_t launch_f_perp(hipStream_t st, bool dbl, const void* psi, int S, int64_t sites, void* out);
+// per sample (mean |F_perp|, mean |F_perp|^2, Larmor-phase winding along x); part: S*rows*3 doubles
+hipError_t launch_texture(hipStream_t st, bool dbl, const void* psi, int S, int64_t rows, int64_t sites, int n,
+                          double* part, double* out);
 // the paper's local sub-steps (4)-(5) over dt at every site
 hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double dt, double c0,
                               double c1, double q);

@@ -839,6 +839,70 @@ __global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sit
   }
 }
 
+// --------------------------------------------------------------------------
+// Real-space transverse spin (Fig. 1): F_perp = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1)
+// per site, and per x-row the FP64 sums of |F_perp|, |F_perp|^2 and of the
+// Larmor-phase steps phi_L(x+1) - phi_L(x) taken in [-pi, pi) (periodic in x).
+// --------------------------------------------------------------------------
+template <typename Real>
+__device__ __forceinline__ Cx<Real> f_perp_at(const Cx<Real>* psi, int64_t sites, int64_t i) {
+  const Cx<Real> p1 = psi[i], p0 = psi[sites + i], pm = psi[2 * sites + i];
+  return scale(cmulc(p1, p0) + cmulc(p0, pm), Real(1.41421356237309504880));
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_f_perp(const Cx<Real>* psi, int S, int64_t sites, Cx<Real>* out) {
+  const int64_t total = int64_t(S) * sites;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t s = i / sites, x = i - s * sites;
+    out[i] = f_perp_at(psi + s * 3 * sites, sites, x);
+  }
+}
+
+// one workgroup per x-row of N sites: part[row] = (sum |F|, sum |F|^2, sum of phase steps)
+template <typename Real>
+__global__ __launch_bounds__(256) void k_texture_rows(const Cx<Real>* psi, int64_t rows, int64_t sites, int n,
+                                                      double* part) {
+  __shared__ double scratch[8];
+  const int64_t row = blockIdx.x;
+  const int64_t s = row / rows, r = row - s * rows;
+  const Cx<Real>* base = psi + s * 3 * sites;
+  const int64_t x0 = r * n;
+  constexpr double kTwoPi = 6.28318530717958647693;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const Cx<Real> z = f_perp_at(base, sites, x0 + j);
+    const Cx<Real> zn = f_perp_at(base, sites, x0 + (j + 1 == n ? 0 : j + 1));
+    const double zr = double(z.re), zi = double(z.im);
+    const double m2 = zr * zr + zi * zi;
+    a[0] += sqrt(m2);
+    a[1] += m2;
+    double d = atan2(double(zn.im), double(zn.re)) - atan2(zi, zr);
+    d -= kTwoPi * floor((d + 0.5 * kTwoPi) / kTwoPi);
+    a[2] += d;
+  }
+  double tot[3];
+  for (int i = 0; i < 3; ++i) tot[i] = block_sum(a[i], scratch);
+  if (threadIdx.x == 0)
+    for (int i = 0; i < 3; ++i) part[row * 3 + i] = tot[i];
+}
+
+// per sample, rows summed in order: (mean |F|, mean |F|^2, winding)
+__global__ __launch_bounds__(256) void k_texture_finish(const double* part, int64_t rows, int64_t sites, double* out) {
+  __shared__ double scratch[8];
+  const int64_t s = blockIdx.x;
+  double a[3] = {0.0, 0.0, 0.0};
+  for (int64_t r = threadIdx.x; r < rows; r += blockDim.x)
+    for (int i = 0; i < 3; ++i) a[i] += part[(s * rows + r) * 3 + i];
+  double tot[3];
+  for (int i = 0; i < 3; ++i) tot[i] = block_sum(a[i], scratch);
+  if (threadIdx.x == 0) {
+    out[s * 3 + 0] = tot[0] / double(sites);
+    out[s * 3 + 1] = tot[1] / double(sites);
+    out[s * 3 + 2] = tot[2] / 6.28318530717958647693;
+  }
+}
+
 template <typename Real>
 __global__ __launch_bounds__(256) void k_paper_local(Cx<Real>* psi, int S, int64_t sites, Real dt, Real c0, Real c1,
                                                      Real q) {
@@ -1390,6 +1454,32 @@ hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_
   else
     hipLaunchKernelGGL(k_paper_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
                        float(dt), float(c0), float(c1), float(q));
+  return hipGetLastError();
+}
+
+hipError_t launch_f_perp(hipStream_t st, bool dbl, const void* psi, int S, int64_t sites, void* out) {
+  const unsigned blocks = grid_for(int64_t(S) * sites, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_f_perp<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi), S,
+                       sites, static_cast<Cx<double>*>(out));
+  else
+    hipLaunchKernelGGL(k_f_perp<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi), S, sites,
+                       static_cast<Cx<float>*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_texture(hipStream_t st, bool dbl, const void* psi, int S, int64_t rows, int64_t sites, int n,
+                          double* part, double* out) {
+  const unsigned blocks = unsigned(int64_t(S) * rows);
+  if (dbl)
+    hipLaunchKernelGGL(k_texture_rows<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
+                       rows, sites, n, part);
+  else
+    hipLaunchKernelGGL(k_texture_rows<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
+                       rows, sites, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_texture_finish, dim3(unsigned(S)), dim3(256), 0, st, part, rows, sites, out);
   return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
     "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
-    "spin1_observables", "spin1_step_observed", "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
+    "spin1_observables", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
+    "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
     "spin1_num_variants", "spin1_autotune", "spin1_get_variant", "spin1_set_variant", "spin1_last_error",
 ]
@@ -80,6 +81,8 @@ def load():
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step_observed": (ctypes.c_int, [vp, i64, f64, i32, vp]),
+        "spin1_transverse_spin": (ctypes.c_int, [vp, i32, vp]),
+        "spin1_spin_texture": (ctypes.c_int, [vp, i32, vp]),
         "spin1_local_update": (ctypes.c_int, [vp, f64]),
         "spin1_set_option": (ctypes.c_int, [vp, i32, i64]),
         "spin1_adjoint_workspace_bytes": (sz, [gp, i32, i64]),
@@ -204,6 +207,14 @@ def observables(ctx, group, obs_ptr):
 
 def step_observed(ctx, n, dt, group, obs_ptr):
     _check(load().spin1_step_observed(ctx, int(n), float(dt), int(group), ctypes.c_void_p(int(obs_ptr))))
+
+
+def transverse_spin(ctx, group, out_ptr):
+    _check(load().spin1_transverse_spin(ctx, int(group), ctypes.c_void_p(int(out_ptr))))
+
+
+def spin_texture(ctx, group, out_ptr):
+    _check(load().spin1_spin_texture(ctx, int(group), ctypes.c_void_p(int(out_ptr))))
 
 
 def local_update(ctx, tau):
@@ -446,6 +457,22 @@ class Sim:
         with self.torch.cuda.stream(self.stream):
             return out.cpu().numpy()
 
+
+    def transverse_spin(self, group=0):
+        """F_perp per site of `group` as a device tensor [S, spatial...]."""
+        g = self.grids[group]
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((g.samples,) + _spatial(g), dtype=self.psi[group].dtype, device=self.device)
+        transverse_spin(self.ctx, group, out.data_ptr())
+        return out
+
+    def spin_texture(self, group=0):
+        """Per-sample (mean |F_perp|, mean |F_perp|^2, Q_w) [S, 3] as numpy."""
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
+        spin_texture(self.ctx, group, out.data_ptr())
+        with self.torch.cuda.stream(self.stream):
+            return out.cpu().numpy()
 
     def step_observed(self, n, dt, group=0):
         """n steps, returning the per-step FP64 (N, F_z, E) of `group` as a

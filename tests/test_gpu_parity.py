@@ -310,6 +310,42 @@ def test_paper_scheme_first_order_and_limits(lib):
         sim.set_option(lib.OPT_SCHEME, 7)
 
 
+# ------------------------------------------------------------------ real-space spin texture
+@pytest.mark.parametrize("grid", [(1, (256,), 0.5, 3), (2, (64, 32), 0.5, 2), (3, (16, 8, 16), 0.5, 2)])
+def test_spin_texture_matches_oracle(lib, grid):
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(19, og.shape, noise=0.8)
+    ref_fp = O.f_perp(psi0)
+    ref = O.spin_texture(psi0, og)
+    for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
+        sim = run_gpu(lib, grid, P1, dtype, psi0=psi0)
+        fp = sim.transverse_spin().cpu().numpy()
+        assert rel(fp, ref_fp) < tol, dtype
+        tex = sim.spin_texture()
+        assert np.allclose(tex[:, :2], ref[:, :2], rtol=tol), dtype
+        if dtype == "c128":
+            assert np.allclose(tex[:, 2], ref[:, 2], atol=1e-9)
+        # the winding of a periodic row is an integer
+        assert np.allclose(tex[:, 2], np.round(tex[:, 2]), atol=1e-6 if dtype == "c64" else 1e-9)
+
+
+@pytest.mark.parametrize("w", [-2, 3])
+def test_spin_texture_of_helix_and_after_steps(lib, w):
+    grid = (1, (512,), 0.5, 2)
+    og = O.Grid(1, (512,), 0.5, 2)
+    psi = O.spin_helix(og, w)
+    for dtype in ("c128", "c64"):
+        sim = run_gpu(lib, grid, P1, dtype, psi0=psi)
+        tex = sim.spin_texture()
+        assert np.allclose(tex[:, 2], w, atol=1e-6) and np.allclose(tex[:, 0], 1.0, rtol=1e-6)
+    # a Wigner run keeps integer windings
+    sim = run_gpu(lib, grid, P1, "c128", seed=20, nsteps=200, dt=0.02)
+    q = sim.spin_texture()[:, 2]
+    assert np.allclose(q, np.round(q), atol=1e-9)
+    og2 = O.Grid(1, (512,), 0.5, 2)
+    assert np.allclose(q, O.spin_texture(sim.fields()[0], og2)[:, 2], atol=1e-9)
+
+
 # ------------------------------------------------------------------ structure factor
 @pytest.mark.parametrize("grid", [(1, (256,), 0.5, 4), (2, (32, 64), 0.5, 3), (3, (16, 16, 8), 0.5, 2),
                                   (1, (4096,), 0.5, 2), (2, (256, 256), 0.5, 1)])
