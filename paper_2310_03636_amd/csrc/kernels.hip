@@ -22,7 +22,7 @@ namespace spin1 {
 // launch configurations
 // --------------------------------------------------------------------------
 // x-pass: radix R, N/R threads per pencil, P pencils per workgroup; STREAM
-// selects the persistent prefetching kernel for the step pass.  V picks one of
+// selects the persistent streaming kernel for the step pass.  V picks one of
 // the step-pass variants the autotuner times: workgroups of about 256 (V = 0),
 // 128 (V = 1) or 512 (V = 2) threads.
 template <int N, typename Real, int V = 0>
@@ -435,11 +435,14 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
 
 // --------------------------------------------------------------------------
 // Streaming (persistent) variants of the step passes.  A grid of about
-// (CUs x resident workgroups) walks the work items with a stride of gridDim.x;
-// while item i is transformed, the global loads of item i + gridDim.x are
-// already in flight, so HBM traffic overlaps the FFT arithmetic even at one or
-// two resident workgroups per CU.  Every item is owned by exactly one
-// workgroup, so reading the next item early sees the pre-pass state.
+// (CUs x resident workgroups) walks the work items with a stride of gridDim.x.
+// The strided pass prefetches: while item i is transformed, the global loads
+// of item i + gridDim.x are already in flight, so HBM traffic overlaps the FFT
+// arithmetic even at one or two resident workgroups per CU.  Every item is
+// owned by exactly one workgroup, so reading the next item early sees the
+// pre-pass state.  The x-pass does not: without the second register set it
+// fits three wavefronts per SIMD instead of two, and the other wavefronts
+// cover its loads (measured 4-6% faster on 256- and 512-point pencils).
 // --------------------------------------------------------------------------
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
@@ -535,18 +538,11 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   };
   int64_t g = blockIdx.x;
   if (g >= groups) return;
-  C nxt[3][R];
-  if (g * P + p < npen) load3(nxt, g * P + p);
   for (; g < groups; g += gridDim.x) {
     const int64_t pid = g * P + p;
     const bool active = pid < npen;
     C v[3][R];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-      for (int e = 0; e < R; ++e) v[m][e] = nxt[m][e];
-    const int64_t next = g + gridDim.x;
-    if (next < groups && next * P + p < npen) load3(nxt, next * P + p);
+    if (active) load3(v, pid);
     if (a.tau_pre != 0.0) {
       const Real tau = Real(a.tau_pre);
 #pragma unroll
