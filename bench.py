@@ -100,6 +100,50 @@ def fp32_vs_fp64_error():
     return err
 
 
+def plain_twiddles_run(steps):
+    """The main workload with once-rounded FP32 stage twiddles (an option of
+    the library): rate from the captured graph, per-pass times, and the field
+    error against the FP64 path after 100 split steps."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    w = WORKLOAD
+    grid = (w["dim"], w["n"], w["dx"], w["samples"])
+    ref = spin1.Sim([grid], w["params"], dtype="c128")
+    ref.init_wigner(w["seed"])
+    ref.step(w["split_steps"], w["dt"])
+    ref.synchronize()
+    r = ref.psi[0].clone()
+    ref.close()
+    sim = spin1.Sim([grid], w["params"], dtype="c64")
+    sim.set_option(spin1.OPT_FP32_TWIDDLES, spin1.TWIDDLES_PLAIN)
+    sim.init_wigner(w["seed"])
+    variants = sim.autotune(reps=2)
+    sim.step(w["split_steps"], w["dt"])
+    sim.synchronize()
+    err = (torch.linalg.vector_norm(sim.psi[0].to(torch.complex128) - r) / torch.linalg.vector_norm(r)).item()
+    del r
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(steps):
+        sim.step(w["split_steps"], w["dt"])
+    e1.record(sim.stream)
+    sim.synchronize()
+    ms = e0.elapsed_time(e1)
+    spin1.profile_read(sim.ctx)
+    spin1.profile_enable(sim.ctx, True)
+    sim.step(w["split_steps"], w["dt"])
+    sim.synchronize()
+    prof = spin1.profile_read(sim.ctx)
+    spin1.profile_enable(sim.ctx, False)
+    sim.close()
+    torch.cuda.empty_cache()
+    sites = w["n"][0] * w["n"][1] * w["samples"]
+    return {"value": sites * w["split_steps"] * steps / (ms / 1e3), "unit": "site-steps/s",
+            "err_fp32_vs_fp64_rel_l2_100_split_steps": err, "variants": variants,
+            "avg_ms": {k: v[0] / v[1] for k, v in prof.items() if v[1] and k in ("xpass", "ypass")}}
+
+
 ADJOINT = dict(n=(256, 256), samples=16, steps=500, dt=0.02, every=23, k_cut=1.0,
                params=dict(c0=1.0, c1=-0.1, q=0.09, n0=1.0, wigner_var=0.5), seed=1005)
 
@@ -338,6 +382,7 @@ def main():
     torch.cuda.empty_cache()
 
     err = fp32_vs_fp64_error()
+    plain = plain_twiddles_run(args.steps)
     adj = adjoint_timing()
     others = other_configs()
 
@@ -378,6 +423,7 @@ def main():
         "adjoint": adj,
         "other_configs": others,
         "err_fp32_vs_fp64_rel_l2_100_split_steps": err,
+        "fp32_plain_twiddles": plain,
         "wall_s": wall,
         "cpu_baseline": cpu,
     }

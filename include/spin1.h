@@ -228,15 +228,25 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   Eq. (5) with couplings averaged over the field and a one-step predictor.
  *   First order in dt; it converges to the same flow as dt -> 0.  Reverse
  *   mode and spin1_step_observed take the Strang scheme only
- *   (SPIN1_EUNSUPPORTED otherwise). */
+ *   (SPIN1_EUNSUPPORTED otherwise).
+ * SPIN1_OPT_FP32_TWIDDLES (complex64 only): SPIN1_TWIDDLES_COMPENSATED
+ *   (default) multiplies by the FFT stage twiddles as hi+lo float pairs, so
+ *   the constants carry no rounding of their own; SPIN1_TWIDDLES_PLAIN rounds
+ *   each twiddle once to a float pair, which halves the cost of those
+ *   multiplies but adds a rounding that repeats identically in every step and
+ *   so accumulates linearly (the phase tables and the radix constants stay
+ *   compensated either way).  Applies to the streaming step passes of
+ *   spin1_step; the other passes keep compensated twiddles. */
 enum spin1_option {
   SPIN1_OPT_GRAPHS = 0,
   SPIN1_OPT_GRAPH_MAX_STEPS = 1,
   SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2,
   SPIN1_OPT_GROUPED_X = 3,
-  SPIN1_OPT_SCHEME = 4
+  SPIN1_OPT_SCHEME = 4,
+  SPIN1_OPT_FP32_TWIDDLES = 5
 };
 enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
+enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_PLAIN = 1 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 
 /* Kernel kinds reported by the profiling hooks. */

@@ -217,6 +217,7 @@ struct spin1_ctx {
   int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
   bool grouped_x = true;
   int scheme = SPIN1_SCHEME_STRANG;
+  bool plain_twiddles = false;
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -359,7 +360,11 @@ int log2_of(int n) {
   return r;
 }
 
-int variant_of(spin1_ctx* ctx, int pass, int n) { return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)]; }
+int twiddle_offset(const spin1_ctx* ctx) { return ctx->plain_twiddles && !ctx->dbl ? kPlainTwiddles : 0; }
+
+int variant_of(spin1_ctx* ctx, int pass, int n) {
+  return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)] + twiddle_offset(ctx);
+}
 
 // the passes of a step after the x-pass: y/z passes, closing half step (2D/3D)
 int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double tau_close) {
@@ -1037,7 +1042,7 @@ int spin1_get_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t* variant)
   int rc = check_variant_args(ctx, pass, n);
   if (rc) return rc;
   if (!variant) return fail(SPIN1_EINVAL, "variant pointer is NULL");
-  *variant = variant_of(ctx, pass, n);
+  *variant = ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)];
   return SPIN1_OK;
 }
 
@@ -1091,10 +1096,10 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
             XPassArgs xa = xargs(ctx, G);
             xa.psi = scratch_dev;
             xa.tau_pre = dt;
-            return launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, v);
+            return launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, v + twiddle_offset(ctx));
           }
           const SPassArgs sa = sargs(ctx, G, axis, scratch_dev, int64_t(3) * G.geo.S);
-          return launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[axis], sa, v);
+          return launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[axis], sa, v + twiddle_offset(ctx));
         };
         e = launch();  // warm-up (also loads the code object)
         if (e == hipSuccess) e = hipEventRecord(ev[0], ctx->stream);
@@ -1141,6 +1146,12 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
     case SPIN1_OPT_SCHEME:
       if (value != SPIN1_SCHEME_STRANG && value != SPIN1_SCHEME_PAPER) return fail(SPIN1_EINVAL, "unknown scheme");
       ctx->scheme = int(value);
+      ctx->version++;
+      return SPIN1_OK;
+    case SPIN1_OPT_FP32_TWIDDLES:
+      if (value != SPIN1_TWIDDLES_COMPENSATED && value != SPIN1_TWIDDLES_PLAIN)
+        return fail(SPIN1_EINVAL, "unknown twiddle precision");
+      ctx->plain_twiddles = value == SPIN1_TWIDDLES_PLAIN;
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_GROUPED_X:

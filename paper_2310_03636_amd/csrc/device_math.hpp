@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace spin1 {
 
 template <typename Real>
@@ -64,6 +66,12 @@ __device__ __forceinline__ Cx<float> mul_tab(Cx<float> x, TabEntry<float> w) {
 }
 __device__ __forceinline__ Cx<double> mul_tab(Cx<double> x, TabEntry<double> w) {
   return {x.re * w.hr - x.im * w.hi, x.re * w.hi + x.im * w.hr};
+}
+
+// multiply by a table value kept as one plain complex number (rounded once)
+template <typename Real>
+__device__ __forceinline__ Cx<Real> mul_tab(Cx<Real> x, Cx<Real> w) {
+  return x * w;
 }
 
 // x * (c_hi + c_lo) for a real constant given in FP64, compensated in FP32
@@ -211,6 +219,17 @@ struct StagedTwiddles {
 };
 template <int N, int Ns, int Rs, typename Real, int R>
 __device__ __forceinline__ TabEntry<Real> tw_at(const StagedTwiddles<Real, N, R>& tw, int j, int r) {
+  static_assert(Ns >= R, "the first stage has no twiddles");
+  return tw.t[(Ns - R) + (r - 1) * Ns + j];
+}
+
+// the same layout with each twiddle rounded once to a plain complex value
+template <typename Real, int N, int R>
+struct StagedTwiddlesPlain {
+  const Cx<Real>* t;
+};
+template <int N, int Ns, int Rs, typename Real, int R>
+__device__ __forceinline__ Cx<Real> tw_at(const StagedTwiddlesPlain<Real, N, R>& tw, int j, int r) {
   static_assert(Ns >= R, "the first stage has no twiddles");
   return tw.t[(Ns - R) + (r - 1) * Ns + j];
 }

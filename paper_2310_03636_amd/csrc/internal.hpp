@@ -85,6 +85,8 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
 hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
                        double n0, double wigner_var);
 // variant: step-pass variant index (0 = default), ignored by the other modes
+// step-pass variant offset selecting plain (once-rounded) FP32 stage twiddles
+constexpr int kPlainTwiddles = 3;
 hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant = 0);
 hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant = 0);
 int step_variants();

@@ -63,6 +63,7 @@ struct SCfg {
 };
 
 constexpr int kStepVariants = 3;
+static_assert(kPlainTwiddles == kStepVariants, "plain-twiddle variants follow the compensated ones");
 
 int xpass_pencils(int n, bool dbl) {
   switch (n) {
@@ -447,12 +448,13 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
 // prefetch had arrived (the vector-memory counter retires in order).
-template <typename Real, int N, int V>
+template <typename Real, int N, int V, bool PLAIN>
 __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
   constexpr int R = SCfg<N, Real, V>::R, T = SCfg<N, Real, V>::T, TX = SCfg<N, Real, V>::TX;
   __shared__ C lds[N * ColLds<Real, TX>::PITCH];
-  __shared__ TabEntry<Real> tw[N];
+  using TE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
+  __shared__ TE tw[N];
   __shared__ TabEntry<Real> ph[N / 2 + 1];  // the phase is even in k
   const int c = threadIdx.x % TX;
   const int t = threadIdx.x / TX;
@@ -461,7 +463,12 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      if constexpr (PLAIN)
+        tw[i] = C{gtw[i].hr, gtw[i].hi};
+      else
+        tw[i] = gtw[i];
+    }
     for (int i = threadIdx.x; i <= N / 2; i += blockDim.x) ph[i] = gph[i];
     __syncthreads();
   }
@@ -494,20 +501,26 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
 #pragma unroll
       for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
     }
-    fft_halfphase_ifft<Real, N, R>(v, t, L, tw, ph, static_cast<const TabEntry<Real>*>(nullptr));
+    fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), ph,
+                                   static_cast<const TabEntry<Real>*>(nullptr));
 #pragma unroll
     for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
   }
 }
 
-template <typename Real, int N, int V, bool ENABLED = XCfg<N, Real, V>::STREAM>
+// PLAIN: the stage twiddles rounded once to plain complex values (FP32 only):
+// half the multiply cost and LDS of the hi+lo form, at a larger systematic
+// rounding of the transform (see the precision option in spin1.h)
+template <typename Real, int N, int V, bool PLAIN, bool ENABLED = XCfg<N, Real, V>::STREAM>
 __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
  if constexpr (ENABLED) {
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real, V>::R, T = XCfg<N, Real, V>::T, P = XCfg<N, Real, V>::P;
   __shared__ C lds[P * RowPad<N, T>::ROW];
   using TW = StagedTwiddles<Real, N, R>;
-  __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
+  using TE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
+  using TWA = std::conditional_t<PLAIN, StagedTwiddlesPlain<Real, N, R>, TW>;
+  __shared__ TE stw[TW::SIZE > 0 ? TW::SIZE : 1];
   // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
   __shared__ TabEntry<Real> ph[2 * N];
   const int t = threadIdx.x % T;
@@ -516,7 +529,13 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
-    for (int i = threadIdx.x; i < TW::SIZE; i += blockDim.x) stw[i] = gtw[TW::exponent(i)];
+    for (int i = threadIdx.x; i < TW::SIZE; i += blockDim.x) {
+      const TabEntry<Real> w = gtw[TW::exponent(i)];
+      if constexpr (PLAIN)
+        stw[i] = C{w.hr, w.hi};
+      else
+        stw[i] = w;
+    }
     for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) ph[i] = gph[i];
     __syncthreads();
   }
@@ -555,7 +574,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
       }
     }
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, TW{stw}, ph + (m == 1 ? N : 0));
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, TWA{stw}, ph + (m == 1 ? N : 0));
     if (a.tau_post != 0.0) {
       const Real tau = Real(a.tau_post);
 #pragma unroll
@@ -1217,25 +1236,33 @@ static int64_t stream_grid(K kernel, int threads, int64_t items) {
   return items < g ? items : g;
 }
 
-template <typename Real, int N, int V>
+template <typename Real, int N, int V, bool PLAIN>
 static hipError_t xpass_stream_v(hipStream_t st, const XPassArgs& a) {
   constexpr int P = XCfg<N, Real, V>::P;
   const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
   XPassArgs b = a;
   b.lg_rows = ilog2(a.rows);
-  const int64_t grid = stream_grid(k_xpass_stream<Real, N, V>, XCfg<N, Real, V>::THREADS, blocks);
-  hipLaunchKernelGGL((k_xpass_stream<Real, N, V>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS), 0, st, b,
-                     blocks);
+  const int64_t grid = stream_grid(k_xpass_stream<Real, N, V, PLAIN>, XCfg<N, Real, V>::THREADS, blocks);
+  hipLaunchKernelGGL((k_xpass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS), 0,
+                     st, b, blocks);
   return hipGetLastError();
 }
 
+template <typename Real, int N, bool PLAIN>
+static hipError_t xpass_stream_p(hipStream_t st, const XPassArgs& a, int v) {
+  // variants whose tables no longer fit in LDS fall back to the default one
+  if (v == 1 && XCfg<N, Real, 1>::STREAM) return xpass_stream_v<Real, N, 1, PLAIN>(st, a);
+  if (v == 2 && XCfg<N, Real, 2>::STREAM) return xpass_stream_v<Real, N, 2, PLAIN>(st, a);
+  return xpass_stream_v<Real, N, 0, PLAIN>(st, a);
+}
+
+// variant: 0..2 the step-pass variant; + kPlainTwiddles for plain FP32 twiddles
 template <typename Real, int N, int MODE>
 static hipError_t xpass_n(hipStream_t st, const XPassArgs& a, int variant) {
   if constexpr (MODE == MODE_STEP && XCfg<N, Real>::STREAM) {
-    // variants whose tables no longer fit in LDS fall back to the default one
-    if (variant == 1 && XCfg<N, Real, 1>::STREAM) return xpass_stream_v<Real, N, 1>(st, a);
-    if (variant == 2 && XCfg<N, Real, 2>::STREAM) return xpass_stream_v<Real, N, 2>(st, a);
-    return xpass_stream_v<Real, N, 0>(st, a);
+    if constexpr (sizeof(Real) == 4)
+      if (variant >= kPlainTwiddles) return xpass_stream_p<Real, N, true>(st, a, variant - kPlainTwiddles);
+    return xpass_stream_p<Real, N, false>(st, a, variant % kPlainTwiddles);
   } else {
     constexpr int P = XCfg<N, Real>::P;
     const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
@@ -1278,7 +1305,7 @@ hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassAr
   return dbl ? xpass_t<double>(st, mode, n, a, variant) : xpass_t<float>(st, mode, n, a, variant);
 }
 
-template <typename Real, int N, int V>
+template <typename Real, int N, int V, bool PLAIN>
 static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
   constexpr int TX = SCfg<N, Real, V>::TX;
   if (a.inner % TX != 0) return hipErrorInvalidValue;
@@ -1286,18 +1313,25 @@ static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
   SPassArgs b = a;
   b.lg_tiles = ilog2(a.inner / TX);
   b.lg_outer = ilog2(a.outer);
-  const int64_t grid = stream_grid(k_spass_stream<Real, N, V>, SCfg<N, Real, V>::THREADS, blocks);
-  hipLaunchKernelGGL((k_spass_stream<Real, N, V>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0, st, b,
-                     blocks);
+  const int64_t grid = stream_grid(k_spass_stream<Real, N, V, PLAIN>, SCfg<N, Real, V>::THREADS, blocks);
+  hipLaunchKernelGGL((k_spass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0,
+                     st, b, blocks);
   return hipGetLastError();
+}
+
+template <typename Real, int N, bool PLAIN>
+static hipError_t spass_stream_p(hipStream_t st, const SPassArgs& a, int v) {
+  if (v == 1) return spass_stream_v<Real, N, 1, PLAIN>(st, a);
+  if (v == 2) return spass_stream_v<Real, N, 2, PLAIN>(st, a);
+  return spass_stream_v<Real, N, 0, PLAIN>(st, a);
 }
 
 template <typename Real, int N, int MODE>
 static hipError_t spass_n(hipStream_t st, const SPassArgs& a, int variant) {
   if constexpr (MODE == MODE_STEP && SCfg<N, Real>::STREAM) {
-    if (variant == 1) return spass_stream_v<Real, N, 1>(st, a);
-    if (variant == 2) return spass_stream_v<Real, N, 2>(st, a);
-    return spass_stream_v<Real, N, 0>(st, a);
+    if constexpr (sizeof(Real) == 4)
+      if (variant >= kPlainTwiddles) return spass_stream_p<Real, N, true>(st, a, variant - kPlainTwiddles);
+    return spass_stream_p<Real, N, false>(st, a, variant % kPlainTwiddles);
   } else {
     constexpr int TX = SCfg<N, Real>::TX;
     if (a.inner % TX != 0) return hipErrorInvalidValue;
