@@ -236,14 +236,21 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   multiplies but adds a rounding that repeats identically in every step and
  *   so accumulates linearly (the phase tables and the radix constants stay
  *   compensated either way).  Applies to the streaming step passes of
- *   spin1_step; the other passes keep compensated twiddles. */
+ *   spin1_step; the other passes keep compensated twiddles.
+ * SPIN1_OPT_CONCURRENT_GROUPS: 1 (default) = when a grouped x-pass runs,
+ *   spin1_step issues the steps of the remaining groups on a second stream
+ *   of the library's (default priority, created on first use), forked from
+ *   the caller's stream at the start of the call and joined back into it at
+ *   the end, so that they overlap; 0 = everything on the caller's stream.
+ *   Not used while profiling or on the NULL stream.  Same results either way. */
 enum spin1_option {
   SPIN1_OPT_GRAPHS = 0,
   SPIN1_OPT_GRAPH_MAX_STEPS = 1,
   SPIN1_OPT_STEPS_PER_LAUNCH_1D = 2,
   SPIN1_OPT_GROUPED_X = 3,
   SPIN1_OPT_SCHEME = 4,
-  SPIN1_OPT_FP32_TWIDDLES = 5
+  SPIN1_OPT_FP32_TWIDDLES = 5,
+  SPIN1_OPT_CONCURRENT_GROUPS = 6
 };
 enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
 enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_PLAIN = 1 };

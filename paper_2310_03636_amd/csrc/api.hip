@@ -218,6 +218,11 @@ struct spin1_ctx {
   bool grouped_x = true;
   int scheme = SPIN1_SCHEME_STRANG;
   bool plain_twiddles = false;
+  // groups outside the grouped x-pass run on a second stream of default
+  // priority, forked from and joined back into the caller's stream per call
+  bool concurrent = true;
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -230,6 +235,9 @@ struct spin1_ctx {
   ~spin1_ctx() {
     drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -503,25 +511,30 @@ int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
   return SPIN1_OK;
 }
 
-int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
-  if (ctx->scheme == SPIN1_SCHEME_PAPER) return enqueue_steps_paper(ctx, n, dt);
+int ensure_side_stream(spin1_ctx* ctx) {
+  if (ctx->side) return SPIN1_OK;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    ctx->side = nullptr;
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  }
+  if ((e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "hipEventCreateWithFlags");
+  return SPIN1_OK;
+}
+
+// The steps of the groups outside the grouped x-pass: multi-step 1D chunks
+// and one launch sequence per step and group.
+int enqueue_other_groups(spin1_ctx* ctx, const std::vector<char>& in_set, int64_t n, double dt) {
   for (auto& G : ctx->groups)
     if (multi_1d(ctx, G)) {
       const int rc = enqueue_group_multi(ctx, G, n, dt);
       if (rc) return rc;
     }
-  const std::vector<size_t> set = grouped_x_set(ctx);
-  std::vector<char> in_set(ctx->groups.size(), 0);
-  for (size_t g : set) in_set[g] = 1;
   for (int64_t i = 0; i < n; ++i) {
     const double pre = i == 0 ? 0.5 * dt : dt;
     const double close = i == n - 1 ? 0.5 * dt : 0.0;
-    if (!set.empty()) {
-      int rc = enqueue_grouped_x(ctx, set, pre, close);
-      for (size_t g : set)
-        if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close);
-      if (rc) return rc;
-    }
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
       const GroupState& G = ctx->groups[g];
       if (multi_1d(ctx, G) || in_set[g]) continue;
@@ -530,6 +543,47 @@ int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
     }
   }
   return SPIN1_OK;
+}
+
+int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
+  if (ctx->scheme == SPIN1_SCHEME_PAPER) return enqueue_steps_paper(ctx, n, dt);
+  const std::vector<size_t> set = grouped_x_set(ctx);
+  std::vector<char> in_set(ctx->groups.size(), 0);
+  for (size_t g : set) in_set[g] = 1;
+  const bool others = set.size() < ctx->groups.size();
+  // the other groups overlap the grouped ones on the second stream (not while
+  // profiling, whose events time the caller's stream)
+  const bool overlap = ctx->concurrent && !set.empty() && others && !ctx->prof && ctx->stream != nullptr;
+  int rc = SPIN1_OK;
+  if (overlap) {
+    if ((rc = ensure_side_stream(ctx))) return rc;
+    hipError_t e = hipEventRecord(ctx->fork_ev, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "stream fork");
+    hipStream_t main = ctx->stream;
+    ctx->stream = ctx->side;
+    rc = enqueue_other_groups(ctx, in_set, n, dt);
+    ctx->stream = main;
+    // join even after a failed enqueue, so that a capture stays well formed
+    e = hipEventRecord(ctx->join_ev, ctx->side);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "stream join");
+  } else if (others) {
+    if ((rc = enqueue_other_groups(ctx, in_set, n, dt))) return rc;
+  }
+  for (int64_t i = 0; i < n && !set.empty(); ++i) {
+    const double pre = i == 0 ? 0.5 * dt : dt;
+    const double close = i == n - 1 ? 0.5 * dt : 0.0;
+    rc = enqueue_grouped_x(ctx, set, pre, close);
+    for (size_t g : set)
+      if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close);
+    if (rc) break;
+  }
+  if (overlap) {
+    const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
+    if (!rc && e != hipSuccess) return hip_fail(e, "stream join");
+  }
+  return rc;
 }
 
 // Replay (capturing on first use) the graph of n steps of dt.
@@ -1146,6 +1200,10 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
     case SPIN1_OPT_SCHEME:
       if (value != SPIN1_SCHEME_STRANG && value != SPIN1_SCHEME_PAPER) return fail(SPIN1_EINVAL, "unknown scheme");
       ctx->scheme = int(value);
+      ctx->version++;
+      return SPIN1_OK;
+    case SPIN1_OPT_CONCURRENT_GROUPS:
+      ctx->concurrent = value != 0;
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_FP32_TWIDDLES:

@@ -262,6 +262,26 @@ def test_grouped_x_pass_matches_oracle(lib, dtype, tol):
         assert rel(out[1][gi], out[0][gi]) < tol / 10, gi
 
 
+def test_concurrent_groups_match_one_stream(lib):
+    """Groups outside the grouped x-pass on the second stream (forked and
+    joined inside each call, captured into the graph): bit-identical to one
+    stream, over replays with eager work in between."""
+    grids = [(1, (4096,), 0.5, 3), (2, (64, 32), 0.5, 2), (1, (512,), 0.5, 2), (2, (128, 16), 0.5, 2)]
+    sims = []
+    for conc in (1, 0):
+        s = lib.Sim(grids, P1, dtype="c64")
+        s.set_option(lib.OPT_CONCURRENT_GROUPS, conc)
+        s.init_wigner(24)
+        sims.append(s)
+    for rep in range(3):
+        for s in sims:
+            s.step(9, 0.02)
+        fa, fb = sims[0].fields(), sims[1].fields()
+        for gi in range(len(grids)):
+            assert np.array_equal(fa[gi], fb[gi]), (rep, gi)
+        sims[0].observables(1)
+
+
 @pytest.mark.parametrize("grid", [(1, (256,), 0.5, 3), (2, (64, 32), 0.5, 2), (3, (16, 8, 16), 0.5, 2)])
 def test_paper_scheme_matches_oracle(lib, grid):
     """The paper's Lie scheme (kinetic, Eq. (4) phases, Eq. (5) mixing with the
