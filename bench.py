@@ -193,6 +193,10 @@ def adjoint_timing():
 OTHER_CONFIGS = {
     "1d_256_s4_c128": dict(groups=[(1, (256,), 0.5, 4)], dtype="c128", dt=0.01, steps=1000,
                            params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1001),
+    # the paper's production runs: 1D L = 4096 in double precision, 250 runs per GPU
+    # (Sec. 2.2; the runs are independent, so they are one batch here)
+    "1d_4096_s250_c128": dict(groups=[(1, (4096,), 0.5, 250)], dtype="c128", dt=0.01, steps=200,
+                              params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1006),
     "3d_256_s8_c64": dict(groups=[(3, (256, 256, 256), 0.5, 8)], dtype="c64", dt=0.02, steps=20,
                           params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003, log=True),
     # the paper's own Lie scheme (Eqs. (3)-(5) in its order) on the main workload
@@ -300,7 +304,7 @@ def profile_pass():
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_math.hpp"):
+    for f in ("kernels_xstream.hip", "kernels_sstream.hip", "pass_common.hpp", "device_math.hpp"):
         with open(os.path.join(ROOT, "paper_2310_03636_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

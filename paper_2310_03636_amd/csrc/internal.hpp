@@ -1,4 +1,4 @@
-// Internal interface between the C ABI (api.hip) and the kernels (kernels.hip).
+// Internal interface between the C ABI (api.hip) and the kernel units (kernels*.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>

@@ -1,0 +1,301 @@
+// The grouped x-pass over several groups and the 1D multi-step kernel of the
+// spin-1 step (gfx950), with their launchers.
+#include "pass_common.hpp"
+
+namespace spin1 {
+
+// --------------------------------------------------------------------------
+// Grouped x-pass: the step x-passes of several groups (different pencil
+// lengths N) in one persistent launch.  Radix 8 for every N, so each thread
+// holds the same 3 x 8 values whatever the group; a workgroup of 256 threads
+// runs P = 2048 / N pencils of N / 8 threads.  The workgroup walks the
+// concatenated item list with a stride of gridDim.x; items of one group are
+// contiguous, so it reloads the group's tables (staged twiddles, phases) into
+// LDS at most once per group.  The next item is prefetched into registers
+// whatever its group.
+// --------------------------------------------------------------------------
+template <typename Real>
+struct GroupedX {
+  static constexpr int R = 8, THREADS = 256;
+  static constexpr int NMAX = sizeof(Real) == 4 ? 1024 : 512;
+  static constexpr int ROWS_LDS = (THREADS * R / 16) * 17;  // P (N + N/16) for every N >= 16
+  // FP32: two workgroups per CU, as the single-group kernel gets
+  static constexpr int WAVES_PER_EU = sizeof(Real) == 4 ? 2 : 1;
+};
+
+template <typename Real, int N>
+__device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<Real>* lds,
+                                               const TabEntry<Real>* stw, const TabEntry<Real>* ph) {
+  constexpr int R = 8, T = N / R;
+  const int t = tid % T, p = tid / T;
+  RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+    fft_phase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N : 0));
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GroupedX<Real>::WAVES_PER_EU))) void
+k_xpass_grouped(XGroupArgs a) {
+  using C = Cx<Real>;
+  using G = GroupedX<Real>;
+  constexpr int R = G::R, NMAX = G::NMAX;
+  __shared__ C lds[G::ROWS_LDS];
+  __shared__ TabEntry<Real> stw[NMAX - R];
+  __shared__ TabEntry<Real> ph[2 * NMAX];
+  const int tid = threadIdx.x;
+  auto group_of = [&](int64_t item) {
+    int g = 0;
+    while (g + 1 < a.ngroups && item >= a.g[g + 1].item_begin) ++g;
+    return g;
+  };
+  // thread's pencil and lane in group g, item `item`; false if past the group's pencils
+  auto place = [&](int g, int64_t item, int64_t* pid, int* t) {
+    const int T = a.g[g].n / R, P = G::THREADS / T;
+    *t = tid % T;
+    *pid = (item - a.g[g].item_begin) * P + tid / T;
+    return *pid < a.g[g].pencils;
+  };
+  auto comp_base = [&](int g, int64_t pid, int m) -> C* {
+    const XGroupEntry& e = a.g[g];
+    const int64_t s = pid >> e.lg_rows;
+    return static_cast<C*>(e.psi) + (s * 3 + m) * e.sites + (pid & (e.rows - 1)) * e.n;
+  };
+  auto load3 = [&](C (&dst)[3][R], int g, int64_t item) {
+    int64_t pid;
+    int t;
+    if (!place(g, item, &pid, &t)) return;
+    const int T = a.g[g].n / R;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const C* src = comp_base(g, pid, m);
+#pragma unroll
+      for (int e = 0; e < R; ++e) dst[m][e] = src[uint32_t(t + e * T)];
+    }
+  };
+  int64_t item = blockIdx.x;
+  if (item >= a.item_end) return;
+  int cur = -1;
+  C nxt[3][R];
+  load3(nxt, group_of(item), item);
+  const Real c0 = Real(a.c0), c1 = Real(a.c1);
+  for (; item < a.item_end; item += gridDim.x) {
+    const int g = group_of(item);
+    if (g != cur) {  // uniform over the workgroup: every thread has the same item
+      __syncthreads();
+      const int n = a.g[g].n;
+      const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.g[g].tw);
+      const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.g[g].ph);
+      switch (n) {
+        case 16: for (int i = tid; i < 16 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 16, R>::exponent(i)]; break;
+        case 32: for (int i = tid; i < 32 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 32, R>::exponent(i)]; break;
+        case 64: for (int i = tid; i < 64 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 64, R>::exponent(i)]; break;
+        case 128: for (int i = tid; i < 128 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 128, R>::exponent(i)]; break;
+        case 256: for (int i = tid; i < 256 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 256, R>::exponent(i)]; break;
+        case 512: for (int i = tid; i < 512 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 512, R>::exponent(i)]; break;
+        default:
+          if constexpr (NMAX >= 1024)
+            for (int i = tid; i < 1024 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 1024, R>::exponent(i)];
+          break;
+      }
+      for (int i = tid; i < 2 * n; i += G::THREADS) ph[i] = gph[i];
+      __syncthreads();
+      cur = g;
+    }
+    C v[3][R];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+      for (int e = 0; e < R; ++e) v[m][e] = nxt[m][e];
+    const int64_t next = item + gridDim.x;
+    if (next < a.item_end) load3(nxt, group_of(next), next);
+    int64_t pid;
+    int t;
+    const bool active = place(g, item, &pid, &t);
+    if (a.tau_pre != 0.0) {
+      const Real tau = Real(a.tau_pre);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+    switch (a.g[g].n) {
+      case 16: grouped_x_body<Real, 16>(v, tid, lds, stw, ph); break;
+      case 32: grouped_x_body<Real, 32>(v, tid, lds, stw, ph); break;
+      case 64: grouped_x_body<Real, 64>(v, tid, lds, stw, ph); break;
+      case 128: grouped_x_body<Real, 128>(v, tid, lds, stw, ph); break;
+      case 256: grouped_x_body<Real, 256>(v, tid, lds, stw, ph); break;
+      case 512: grouped_x_body<Real, 512>(v, tid, lds, stw, ph); break;
+      default:
+        if constexpr (NMAX >= 1024) grouped_x_body<Real, 1024>(v, tid, lds, stw, ph);
+        break;
+    }
+    if (a.g[g].tau_post != 0.0) {
+      const Real tau = Real(a.g[g].tau_post);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        C site[3] = {v[0][e], v[1][e], v[2][e]};
+        local_update(site, tau, c0, c1);
+        v[0][e] = site[0];
+        v[1][e] = site[1];
+        v[2][e] = site[2];
+      }
+    }
+    if (active) {
+      const int T = a.g[g].n / R;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        C* dst = comp_base(g, pid, m);
+#pragma unroll
+        for (int e = 0; e < R; ++e) dst[uint32_t(t + e * T)] = v[m][e];
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// 1D: several steps per launch.  A 1D sample is one pencil, so a workgroup
+// can keep it in registers for K consecutive split steps with no HBM traffic
+// in between: load, K x [R(tau) -> FFT -> phase -> inverse FFT], optional
+// closing R(dt/2), store.  One pencil per workgroup (the sample count is the
+// parallelism); tables in LDS: twiddles (half table for N = 4096) and the
+// kinetic phase for k <= N/2 (it is even in k), the Zeeman factor
+// exp(-i q dt) applied separately to m = +-1.
+// --------------------------------------------------------------------------
+template <int N, typename Real>
+struct MultiCfg {
+  static constexpr int R = XCfg<N, Real>::R;
+  static constexpr int T = N / R;
+  static constexpr bool HALF_TW = N >= 4096;
+  static constexpr int TW_N = HALF_TW ? N / 2 + 1 : N;
+};
+
+template <typename Real, int N>
+__global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs a, int K, double dt, int open_half,
+                                                                       int close_half) {
+  using C = Cx<Real>;
+  using Cfg = MultiCfg<N, Real>;
+  constexpr int R = Cfg::R, T = Cfg::T;
+  __shared__ C lds[RowPad<N, T>::ROW];
+  __shared__ TabEntry<Real> stw[Cfg::TW_N];
+  __shared__ TabEntry<Real> ph0[N / 2 + 1];
+  __shared__ TabEntry<Real> zq;
+  const int t = threadIdx.x;
+  {
+    const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
+    const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph) + N;  // m = 0 row
+    for (int i = t; i < Cfg::TW_N; i += T) stw[i] = gtw[i];
+    for (int i = t; i <= N / 2; i += T) ph0[i] = gph[i];
+    if (t == 0) {
+      double sn, cs;
+      sincos(a.q * dt, &sn, &cs);
+      store_tab(&zq, cs, -sn);
+    }
+    __syncthreads();
+  }
+  RowLds<Real, N, T, (T <= 64)> L{lds};
+  C* psi = static_cast<C*>(a.psi) + int64_t(blockIdx.x) * 3 * a.sites + t;
+  C v[3][R];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[m][e] = psi[m * a.sites + e * T];
+  const Real c0 = Real(a.c0), c1 = Real(a.c1);
+  auto local_all = [&](Real tau) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      C site[3] = {v[0][e], v[1][e], v[2][e]};
+      local_update(site, tau, c0, c1);
+      v[0][e] = site[0];
+      v[1][e] = site[1];
+      v[2][e] = site[2];
+    }
+  };
+  for (int k = 0; k < K; ++k) {
+    local_all(Real((k == 0 && open_half) ? 0.5 * dt : dt));
+    if constexpr (Cfg::HALF_TW) {
+      const HalfTwiddles<Real, N> tw{stw};
+      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
+      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
+      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
+    } else {
+      const TabEntry<Real>* tw = stw;
+      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
+      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
+      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
+    }
+  }
+  if (close_half) local_all(Real(0.5 * dt));
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int e = 0; e < R; ++e) psi[m * a.sites + e * T] = v[m][e];
+}
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+int step_variants() { return kStepVariants; }
+
+int grouped_x_max_n(bool dbl) { return dbl ? GroupedX<double>::NMAX : GroupedX<float>::NMAX; }
+
+int64_t grouped_x_items(int n, int64_t pencils) {
+  const int P = GroupedX<float>::THREADS * GroupedX<float>::R / n;
+  return (pencils + P - 1) / P;
+}
+
+template <typename Real>
+static hipError_t xpass_grouped_t(hipStream_t st, const XGroupArgs& a) {
+  if (a.ngroups < 1 || a.ngroups > kMaxGroupedX) return hipErrorInvalidValue;
+  for (int g = 0; g < a.ngroups; ++g) {
+    const XGroupEntry& e = a.g[g];
+    if (e.n < 16 || e.n > GroupedX<Real>::NMAX || (e.n & (e.n - 1)) != 0) return hipErrorInvalidValue;
+    const int64_t end = g + 1 < a.ngroups ? a.g[g + 1].item_begin : a.item_end;
+    if (end - e.item_begin != grouped_x_items(e.n, e.pencils)) return hipErrorInvalidValue;
+    if ((e.rows & (e.rows - 1)) != 0 || (int64_t(1) << e.lg_rows) != e.rows) return hipErrorInvalidValue;
+  }
+  if (a.g[0].item_begin != 0 || a.item_end < 1) return hipErrorInvalidValue;
+  const int64_t grid = stream_grid(k_xpass_grouped<Real>, GroupedX<Real>::THREADS, a.item_end);
+  hipLaunchKernelGGL(k_xpass_grouped<Real>, dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a) {
+  return dbl ? xpass_grouped_t<double>(st, a) : xpass_grouped_t<float>(st, a);
+}
+
+template <typename Real, int N>
+static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double dt, bool open_half, bool close_half) {
+  hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
+                     int(open_half), int(close_half));
+  return hipGetLastError();
+}
+
+template <typename Real>
+static hipError_t x1d_multi_t(hipStream_t st, int n, const XPassArgs& a, int K, double dt, bool oh, bool ch) {
+  switch (n) {
+    case 8: return x1d_multi_n<Real, 8>(st, a, K, dt, oh, ch);
+    case 16: return x1d_multi_n<Real, 16>(st, a, K, dt, oh, ch);
+    case 32: return x1d_multi_n<Real, 32>(st, a, K, dt, oh, ch);
+    case 64: return x1d_multi_n<Real, 64>(st, a, K, dt, oh, ch);
+    case 128: return x1d_multi_n<Real, 128>(st, a, K, dt, oh, ch);
+    case 256: return x1d_multi_n<Real, 256>(st, a, K, dt, oh, ch);
+    case 512: return x1d_multi_n<Real, 512>(st, a, K, dt, oh, ch);
+    case 1024: return x1d_multi_n<Real, 1024>(st, a, K, dt, oh, ch);
+    case 2048: return x1d_multi_n<Real, 2048>(st, a, K, dt, oh, ch);
+    case 4096: return x1d_multi_n<Real, 4096>(st, a, K, dt, oh, ch);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
+                            bool close_half) {
+  return dbl ? x1d_multi_t<double>(st, n, a, K, dt, open_half, close_half)
+             : x1d_multi_t<float>(st, n, a, K, dt, open_half, close_half);
+}
+
+}  // namespace spin1
