@@ -513,14 +513,20 @@ int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
 
 int ensure_side_stream(spin1_ctx* ctx) {
   if (ctx->side) return SPIN1_OK;
-  hipError_t e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    ctx->side = nullptr;
-    return hip_fail(e, "hipStreamCreateWithFlags");
+  hipStream_t s = nullptr;
+  hipEvent_t f = nullptr, j = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
+  if (e != hipSuccess) {  // all or nothing
+    if (j) (void)hipEventDestroy(j);
+    if (f) (void)hipEventDestroy(f);
+    if (s) (void)hipStreamDestroy(s);
+    return hip_fail(e, "second stream");
   }
-  if ((e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming)) != hipSuccess ||
-      (e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming)) != hipSuccess)
-    return hip_fail(e, "hipEventCreateWithFlags");
+  ctx->side = s;
+  ctx->fork_ev = f;
+  ctx->join_ev = j;
   return SPIN1_OK;
 }
 
