@@ -262,6 +262,21 @@ def test_grouped_x_pass_matches_oracle(lib, dtype, tol):
         assert rel(out[1][gi], out[0][gi]) < tol / 10, gi
 
 
+def test_more_groups_than_one_grouped_launch_takes(lib):
+    """Nine eligible groups: eight share the grouped x-pass, the ninth runs its
+    own launches (on the second stream); all match the oracle."""
+    sizes = [(16, 16), (32, 16), (16, 32), (64, 16), (16, 64), (32, 32), (128, 16), (16, 128), (64, 32)]
+    grids = [(2, n, 0.5, 1) for n in sizes]
+    sim = lib.Sim(grids, P1, dtype="c128")
+    sim.init_wigner(25)
+    sim.step(6, 0.02)
+    f = sim.fields()
+    for gi, g in enumerate(grids):
+        og = O.Grid(g[0], g[1], g[2], g[3])
+        ref = O.evolve(O.init_wigner(25, og, oparams(P1), group=gi), 6, 0.02, oparams(P1), og)
+        assert rel(f[gi], ref) < 1e-12, gi
+
+
 def test_concurrent_groups_match_one_stream(lib):
     """Groups outside the grouped x-pass on the second stream (forked and
     joined inside each call, captured into the graph): bit-identical to one
