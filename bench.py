@@ -255,6 +255,41 @@ def other_configs():
     return out
 
 
+def full_run():
+    """The 2D workload as specified end to end: 10^4 split steps of the
+    512 x 512 x 64 batch with the radially binned F_perp structure factor every
+    100 steps (101 snapshots, per-sample shell means kept on the device)."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    w = WORKLOAD
+    grid = (w["dim"], w["n"], w["dx"], w["samples"])
+    sim = spin1.Sim([grid], w["params"], dtype="c64")
+    sim.init_wigner(w["seed"])
+    sim.autotune(reps=2)
+    sim.step(100, w["dt"])  # capture the 100-step graph
+    sim.init_wigner(w["seed"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    snaps = [sim.structure_factor_device()]
+    for _ in range(100):
+        sim.step(100, w["dt"])
+        snaps.append(sim.structure_factor_device())
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    sites = w["n"][0] * w["n"][1] * w["samples"]
+    first, last = snaps[0].mean(0), snaps[-1].mean(0)
+    out = {"workload": "2D 512x512, 64 samples, complex64, dt=0.02, 10^4 split steps, S(k) every 100 steps",
+           "wall_ms": ms, "value": sites * 10000 / (ms / 1e3), "unit": "site-steps/s",
+           "snapshots": len(snaps), "S_k1_first_last": [float(first[1]), float(last[1])]}
+    sim.close()
+    del snaps
+    torch.cuda.empty_cache()
+    return out
+
+
 def oracle_baseline(budget_s=20.0):
     """The FP64 oracle on the host: one sample of the 512 x 512 workload,
     split steps until about budget_s seconds have passed."""
@@ -389,6 +424,7 @@ def main():
     plain = plain_twiddles_run(args.steps)
     adj = adjoint_timing()
     others = other_configs()
+    full = full_run()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -426,6 +462,7 @@ def main():
         "speedup_fp32_vs_fp64": value / value64,
         "adjoint": adj,
         "other_configs": others,
+        "full_run": full,
         "err_fp32_vs_fp64_rel_l2_100_split_steps": err,
         "fp32_plain_twiddles": plain,
         "wall_s": wall,
