@@ -212,9 +212,9 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  * SPIN1_OPT_STEPS_PER_LAUNCH_1D: 1D groups run up to this many consecutive
  *   split steps in one launch, each sample held on chip between steps
  *   (range 1..1024); 1 = one x-pass launch per step, as for 2D/3D groups;
- *   0 (default) = automatic: 64 for Nx <= 1024, 1 above (where a sample's
- *   three components no longer fit one workgroup's registers).  The result
- *   is the same map either way (same arithmetic, different kernel).
+ *   0 (default) = automatic: 64 for Nx <= 2048, 1 at 4096 (where a sample no
+ *   longer fits one workgroup's LDS and registers).  The result is the same
+ *   map either way (same arithmetic, different kernel).
  * SPIN1_OPT_GROUPED_X: 1 (default) = when two or more bound groups are
  *   stepped one x-pass launch per step and have Nx in 16..1024 (FP32) or
  *   16..512 (FP64), their x-passes run as one persistent launch per step
@@ -242,7 +242,12 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   of the library's (default priority, created on first use), forked from
  *   the caller's stream at the start of the call and joined back into it at
  *   the end, so that they overlap; 0 = everything on the caller's stream.
- *   Not used while profiling or on the NULL stream.  Same results either way. */
+ *   Not used while profiling or on the NULL stream.  Same results either way.
+ * SPIN1_OPT_1D_KERNEL: the kernel of the multi-step 1D launches: 0 (default)
+ *   and 2 = three thread groups per sample, one per component, regrouped
+ *   through LDS for the local update (shorter step latency; Nx <= 2048, the
+ *   pencil form otherwise); 1 = one thread group per sample holding all three
+ *   components.  Same map either way. */
 enum spin1_option {
   SPIN1_OPT_GRAPHS = 0,
   SPIN1_OPT_GRAPH_MAX_STEPS = 1,
@@ -250,7 +255,8 @@ enum spin1_option {
   SPIN1_OPT_GROUPED_X = 3,
   SPIN1_OPT_SCHEME = 4,
   SPIN1_OPT_FP32_TWIDDLES = 5,
-  SPIN1_OPT_CONCURRENT_GROUPS = 6
+  SPIN1_OPT_CONCURRENT_GROUPS = 6,
+  SPIN1_OPT_1D_KERNEL = 7
 };
 enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
 enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_PLAIN = 1 };

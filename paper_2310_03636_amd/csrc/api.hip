@@ -216,6 +216,7 @@ struct spin1_ctx {
   int64_t graph_max_steps = 1024;
   int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
   bool grouped_x = true;
+  int kernel_1d = 0;  // 0 automatic, 1 one thread group per sample, 2 component groups
   int scheme = SPIN1_SCHEME_STRANG;
   bool plain_twiddles = false;
   // groups outside the grouped x-pass run on a second stream of default
@@ -417,10 +418,15 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
 int steps_per_launch(const spin1_ctx* ctx, const GroupState& G) {
   if (G.geo.dim != 1) return 1;
   if (ctx->steps_per_launch_1d > 0) return ctx->steps_per_launch_1d;
-  return G.geo.n[0] <= 1024 ? 64 : 1;
+  return G.geo.n[0] <= 2048 ? 64 : 1;
 }
 
 bool multi_1d(const spin1_ctx* ctx, const GroupState& G) { return steps_per_launch(ctx, G) > 1; }
+
+// The component-group form of the 1D multi-step kernel unless chosen
+// otherwise (it was faster at every measured size and sample count; where its
+// LDS does not fit, Nx = 4096, the launcher takes the pencil form).
+bool split_1d(const spin1_ctx* ctx, const GroupState&) { return ctx->kernel_1d != 1; }
 
 int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double dt) {
   XPassArgs xa = xargs(ctx, G);
@@ -430,7 +436,7 @@ int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double d
     hipError_t e;
     {
       Prof pr(ctx, SPIN1_K_XPASS);
-      e = launch_x1d_multi(ctx->stream, ctx->dbl, G.geo.n[0], xa, k, dt, i0 == 0, i0 + k == n);
+      e = launch_x1d_multi(ctx->stream, ctx->dbl, G.geo.n[0], xa, k, dt, i0 == 0, i0 + k == n, split_1d(ctx, G));
     }
     if (e != hipSuccess) return hip_fail(e, "1D multi-step pass");
   }
@@ -1206,6 +1212,11 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
     case SPIN1_OPT_SCHEME:
       if (value != SPIN1_SCHEME_STRANG && value != SPIN1_SCHEME_PAPER) return fail(SPIN1_EINVAL, "unknown scheme");
       ctx->scheme = int(value);
+      ctx->version++;
+      return SPIN1_OK;
+    case SPIN1_OPT_1D_KERNEL:
+      if (value < 0 || value > 2) return fail(SPIN1_EINVAL, "1D kernel choice must be 0, 1 or 2");
+      ctx->kernel_1d = int(value);
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_CONCURRENT_GROUPS:

@@ -97,8 +97,10 @@ int64_t grouped_x_items(int n, int64_t pencils);
 hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a);
 // 1D: K split steps of one pencil per workgroup in one launch (open_half: the
 // first step opens with R(dt/2) instead of R(dt); close_half: closing R(dt/2))
+// split: the latency form (three component groups per sample) instead of one
+// thread group holding all three components
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
-                            bool close_half);
+                            bool close_half, bool split);
 hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
 // F_perp per site [S][sites] (field precision)
 hipError_t launch_f_perp(hipStream_t st, bool dbl, const void* psi, int S, int64_t sites, void* out);

@@ -237,6 +237,92 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
 }
 
 // --------------------------------------------------------------------------
+// 1D, latency form: the three components of a sample in three thread groups
+// of T = min(64, N/2) lanes (one wavefront each from N = 128 on), so the three
+// transforms of a step run side by side instead of one after another.  The
+// local update regroups the components through LDS: each group writes its
+// component into its LDS row in natural order, the workgroup synchronises,
+// every thread updates whole sites (all three components), and each group
+// reads its component back.  A group's transforms exchange only within its
+// own row and wavefront.
+// --------------------------------------------------------------------------
+template <int N>
+struct SplitCfg {
+  static constexpr int R = N / 64 > 16 ? 16 : (N / 64 > 2 ? N / 64 : 2);
+  static constexpr int T = N / R;
+  static constexpr int THREADS = 3 * T;
+  static constexpr int ROW = RowPad<N, T>::ROW;
+  // three rows, staged twiddles and the half phase table in 160 KB of LDS
+  template <typename Real>
+  static constexpr bool fits() {
+    return 3 * ROW * int(sizeof(Cx<Real>)) + (N - R + N / 2 + 2) * int(sizeof(TabEntry<Real>)) <= 160 * 1024;
+  }
+};
+
+template <typename Real, int N, bool ENABLED = SplitCfg<N>::template fits<Real>()>
+__global__ __launch_bounds__((SplitCfg<N>::THREADS)) void k_x1d_split(XPassArgs a, int K, double dt, int open_half,
+                                                                       int close_half) {
+ if constexpr (ENABLED) {
+  using C = Cx<Real>;
+  using Cfg = SplitCfg<N>;
+  constexpr int R = Cfg::R, T = Cfg::T, ROW = Cfg::ROW;
+  using TW = StagedTwiddles<Real, N, R>;
+  __shared__ C rows[3 * ROW];
+  __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
+  __shared__ TabEntry<Real> ph0[N / 2 + 1];
+  __shared__ TabEntry<Real> zq;
+  const int tid = threadIdx.x;
+  const int m = tid / T, t = tid - m * T;
+  {
+    const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
+    const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph) + N;  // m = 0 row
+    for (int i = tid; i < TW::SIZE; i += Cfg::THREADS) stw[i] = gtw[TW::exponent(i)];
+    for (int i = tid; i <= N / 2; i += Cfg::THREADS) ph0[i] = gph[i];
+    if (tid == 0) {
+      double sn, cs;
+      sincos(a.q * dt, &sn, &cs);
+      store_tab(&zq, cs, -sn);
+    }
+    __syncthreads();
+  }
+  // up to T = 64 a group never straddles a wavefront (T is a power of two) and
+  // exchanges within it; longer rows synchronise the workgroup, which every
+  // group reaches equally often
+  RowLds<Real, N, T, (T <= 64)> L{rows + m * ROW};
+  C* psi = static_cast<C*>(a.psi) + int64_t(blockIdx.x) * 3 * a.sites + m * a.sites + t;
+  C v[R];
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = psi[e * T];
+  const Real c0 = Real(a.c0), c1 = Real(a.c1);
+  const TabEntry<Real>* zm = m == 1 ? nullptr : &zq;
+  auto local_all = [&](Real tau) {
+#pragma unroll
+    for (int e = 0; e < R; ++e) L.store(t + e * T, v[e]);
+    __syncthreads();
+    for (int s = tid; s < N; s += Cfg::THREADS) {
+      const int i = RowPad<N, T>::at(s);
+      C site[3] = {rows[i], rows[ROW + i], rows[2 * ROW + i]};
+      local_update(site, tau, c0, c1);
+      rows[i] = site[0];
+      rows[ROW + i] = site[1];
+      rows[2 * ROW + i] = site[2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < R; ++e) v[e] = L.load(t + e * T);
+    // the group's next LDS writes (its own row) follow these reads in order
+  };
+  for (int k = 0; k < K; ++k) {
+    local_all(Real((k == 0 && open_half) ? 0.5 * dt : dt));
+    fft_halfphase_ifft<Real, N, R>(v, t, L, TW{stw}, ph0, zm);
+  }
+  if (close_half) local_all(Real(0.5 * dt));
+#pragma unroll
+  for (int e = 0; e < R; ++e) psi[e * T] = v[e];
+ }
+}
+
+// --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
 int step_variants() { return kStepVariants; }
@@ -269,33 +355,40 @@ hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a) {
 }
 
 template <typename Real, int N>
-static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double dt, bool open_half, bool close_half) {
-  hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
-                     int(open_half), int(close_half));
+static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double dt, bool open_half, bool close_half,
+                              bool split) {
+  // the latency form where its LDS fits (every size but 4096), else the pencil form
+  if (split && SplitCfg<N>::template fits<Real>())
+    hipLaunchKernelGGL((k_x1d_split<Real, N>), dim3(unsigned(a.S)), dim3(SplitCfg<N>::THREADS), 0, st, a, K, dt,
+                       int(open_half), int(close_half));
+  else
+    hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
+                       int(open_half), int(close_half));
   return hipGetLastError();
 }
 
 template <typename Real>
-static hipError_t x1d_multi_t(hipStream_t st, int n, const XPassArgs& a, int K, double dt, bool oh, bool ch) {
+static hipError_t x1d_multi_t(hipStream_t st, int n, const XPassArgs& a, int K, double dt, bool oh, bool ch,
+                               bool sp) {
   switch (n) {
-    case 8: return x1d_multi_n<Real, 8>(st, a, K, dt, oh, ch);
-    case 16: return x1d_multi_n<Real, 16>(st, a, K, dt, oh, ch);
-    case 32: return x1d_multi_n<Real, 32>(st, a, K, dt, oh, ch);
-    case 64: return x1d_multi_n<Real, 64>(st, a, K, dt, oh, ch);
-    case 128: return x1d_multi_n<Real, 128>(st, a, K, dt, oh, ch);
-    case 256: return x1d_multi_n<Real, 256>(st, a, K, dt, oh, ch);
-    case 512: return x1d_multi_n<Real, 512>(st, a, K, dt, oh, ch);
-    case 1024: return x1d_multi_n<Real, 1024>(st, a, K, dt, oh, ch);
-    case 2048: return x1d_multi_n<Real, 2048>(st, a, K, dt, oh, ch);
-    case 4096: return x1d_multi_n<Real, 4096>(st, a, K, dt, oh, ch);
+    case 8: return x1d_multi_n<Real, 8>(st, a, K, dt, oh, ch, sp);
+    case 16: return x1d_multi_n<Real, 16>(st, a, K, dt, oh, ch, sp);
+    case 32: return x1d_multi_n<Real, 32>(st, a, K, dt, oh, ch, sp);
+    case 64: return x1d_multi_n<Real, 64>(st, a, K, dt, oh, ch, sp);
+    case 128: return x1d_multi_n<Real, 128>(st, a, K, dt, oh, ch, sp);
+    case 256: return x1d_multi_n<Real, 256>(st, a, K, dt, oh, ch, sp);
+    case 512: return x1d_multi_n<Real, 512>(st, a, K, dt, oh, ch, sp);
+    case 1024: return x1d_multi_n<Real, 1024>(st, a, K, dt, oh, ch, sp);
+    case 2048: return x1d_multi_n<Real, 2048>(st, a, K, dt, oh, ch, sp);
+    case 4096: return x1d_multi_n<Real, 4096>(st, a, K, dt, oh, ch, sp);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
-                            bool close_half) {
-  return dbl ? x1d_multi_t<double>(st, n, a, K, dt, open_half, close_half)
-             : x1d_multi_t<float>(st, n, a, K, dt, open_half, close_half);
+                            bool close_half, bool split) {
+  return dbl ? x1d_multi_t<double>(st, n, a, K, dt, open_half, close_half, split)
+             : x1d_multi_t<float>(st, n, a, K, dt, open_half, close_half, split);
 }
 
 }  // namespace spin1

@@ -34,6 +34,7 @@ OPT_GRAPHS, OPT_GRAPH_MAX_STEPS, OPT_STEPS_PER_LAUNCH_1D, OPT_GROUPED_X, OPT_SCH
 SCHEME_STRANG, SCHEME_PAPER = 0, 1
 OPT_FP32_TWIDDLES = 5
 OPT_CONCURRENT_GROUPS = 6
+OPT_1D_KERNEL = 7
 TWIDDLES_COMPENSATED, TWIDDLES_PLAIN = 0, 1
 
 KERNEL_KINDS = ["xpass", "ypass", "zpass", "local", "spectrum", "shells", "observables", "other"]

@@ -79,24 +79,26 @@ def test_one_step_1d_all_sizes(lib, n, per_launch):
         assert rel(sim.fields()[0], ref) < tol, dtype
 
 
-@pytest.mark.parametrize("n", [8, 64, 256, 1024, 2048, 4096])
+@pytest.mark.parametrize("n", [8, 16, 64, 256, 512, 1024, 2048, 4096])
 def test_multi_step_1d_chunks_match_oracle(lib, n):
     """23 steps as launches of 7, 7, 7 and 2 steps (first opens, last closes
-    with a half step) against the oracle and against one launch per step."""
+    with a half step), in both multi-step kernels, against the oracle and
+    against one launch per step."""
     grid = (1, (n,), 0.5, 3)
     og = O.Grid(1, (n,), 0.5, 3)
     psi0 = random_field(n + 1, og.shape, noise=0.4)
     ref = O.evolve(psi0, 23, 0.01, oparams(P1), og)
     for dtype, tol, tol_pair in (("c128", 1e-12, 1e-13), ("c64", 1e-5, 5e-6)):
         out = {}
-        for per_launch in (1, 7):
+        for per_launch, kern in ((1, 0), (7, 1), (7, 2)):
             sim = lib.Sim([grid], P1, dtype=dtype)
             sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, per_launch)
+            sim.set_option(lib.OPT_1D_KERNEL, kern)
             sim.set_fields([psi0])
             sim.step(23, 0.01)
-            out[per_launch] = sim.fields()[0]
-            assert rel(out[per_launch], ref) < tol, (dtype, per_launch)
-        assert rel(out[7], out[1]) < tol_pair, dtype
+            out[kern] = sim.fields()[0]
+            assert rel(out[kern], ref) < tol, (dtype, per_launch, kern)
+        assert rel(out[1], out[0]) < tol_pair and rel(out[2], out[0]) < tol_pair, dtype
 
 
 def test_multi_step_1d_graph_and_option(lib):
