@@ -169,7 +169,7 @@ def k_squared(grid):
 # --------------------------------------------------------------------------
 # initial state: polar condensate plus Wigner noise (Sec. 2.1 and Sec. 2.2)
 # --------------------------------------------------------------------------
-def init_wigner(seed, grid, p, group=0):
+def init_wigner(seed, grid, p, group=0, samples=None):
     """psi_m(x_j) = sqrt(n0) delta_{m0} + delta psi_{m,j}.
 
     The paper starts each run from a weakly fluctuating state with vanishing
@@ -178,19 +178,21 @@ def init_wigner(seed, grid, p, group=0):
     <|delta psi|^2> = w / dx^d per site and component (half a quantum per mode
     for w = 1/2).  Each number comes from one Philox4x64-10 block with
     counter (site, component, sample, group) and key (seed, 0); words 0 and 1
-    feed Box-Muller.
+    feed Box-Muller.  samples: optional list of sample indices to generate
+    (rows of the result in that order); all samples by default.
     """
     spatial = grid.spatial
     nsite = grid.sites
     site = np.arange(nsite, dtype=np.uint64).reshape(spatial)
-    psi = np.empty(grid.shape, dtype=np.complex128)
+    which = list(range(grid.samples)) if samples is None else list(samples)
+    psi = np.empty((len(which), 3) + spatial, dtype=np.complex128)
     amp = np.sqrt(p.wigner_var / (2.0 * grid.cell))
-    for s in range(grid.samples):
+    for i, s in enumerate(which):
         for c in range(3):
             ctr = (site, np.uint64(c), np.uint64(s), np.uint64(group))
             g_re, g_im = gaussian_pair(ctr, (np.uint64(seed), np.uint64(0)))
-            psi[s, c] = amp * (g_re + 1j * g_im)
-        psi[s, 1] += np.sqrt(p.n0)
+            psi[i, c] = amp * (g_re + 1j * g_im)
+        psi[i, 1] += np.sqrt(p.n0)
     return psi
 
 

@@ -1,0 +1,95 @@
+"""The benchmark workloads at their full sizes, in the launch configuration
+the benchmark times (autotuned variants, captured step graphs): sampled Wigner
+runs against the oracle run on those samples alone (the runs are independent),
+and properties that hold at any size where the oracle would take minutes.
+
+Tolerances: complex64 after two split steps, 1e-5 relative L2 per checked
+sample (one step holds 2e-6 in the small-size tests)."""
+import numpy as np
+import pytest
+
+from oracle import spin1 as O
+
+pytestmark = pytest.mark.gpu
+
+P2 = dict(c0=1.0, c1=-0.1, q=0.09, n0=1.0, wigner_var=0.5)
+
+
+def oparams(p):
+    return O.Params(p["c0"], p["c1"], p["q"], p["n0"], p["wigner_var"])
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_samples(seed, g, p, group, which, nsteps, dt):
+    og = O.Grid(g[0], g[1], g[2], g[3])
+    psi = O.init_wigner(seed, og, oparams(p), group=group, samples=which)
+    sub = O.Grid(g[0], g[1], g[2], len(which))
+    return O.evolve(psi, nsteps, dt, oparams(p), sub)
+
+
+def test_2d_512_64_samples_full_size(lib):
+    g = (2, (512, 512), 0.5, 64)
+    sim = lib.Sim([g], P2, dtype="c64")
+    sim.init_wigner(1002)
+    sim.autotune(reps=1)
+    sim.step(2, 0.02)
+    which = [0, 37, 63]
+    got = sim.psi[0][which].cpu().numpy().astype(np.complex128)
+    ref = oracle_samples(1002, g, P2, 0, which, 2, 0.02)
+    for i, s in enumerate(which):
+        assert rel(got[i], ref[i]) < 1e-5, s
+
+
+def test_uneven_batch_full_size(lib):
+    """The four groups of the uneven workload in one plan (grouped x-pass,
+    1D group on the second stream): first and last sample of every group."""
+    groups = [(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
+              (2, (1024, 1024), 0.5, 4)]
+    sim = lib.Sim(groups, P2, dtype="c64")
+    sim.init_wigner(1004)
+    sim.autotune(reps=1)
+    sim.step(2, 0.02)
+    for gi, g in enumerate(groups):
+        which = [0, g[3] - 1]
+        got = sim.psi[gi][which].cpu().numpy().astype(np.complex128)
+        ref = oracle_samples(1004, g, P2, gi, which, 2, 0.02)
+        for i, s in enumerate(which):
+            assert rel(got[i], ref[i]) < 1e-5, (gi, s)
+
+
+def test_3d_256_8_samples_full_size_invariants(lib):
+    """256^3 x 8 (3 GiB of complex64): one oracle step takes minutes per
+    sample, so the full-size check is by properties: norm and F_z per sample
+    conserved, and 10 steps forward then 10 back return the initial state
+    (the map is time-reversible)."""
+    p3 = dict(c0=1.0, c1=-0.05, q=0.025, n0=1.0, wigner_var=0.5)
+    g = (3, (256, 256, 256), 0.5, 8)
+    sim = lib.Sim([g], p3, dtype="c64")
+    sim.init_wigner(1003)
+    sim.autotune(reps=1)
+    psi0 = sim.psi[0].clone()
+    obs0 = sim.observables()
+    sim.step(10, 0.02)
+    obs1 = sim.observables()
+    assert np.allclose(obs1[:, 0], obs0[:, 0], rtol=1e-5)
+    assert np.allclose(obs1[:, 1], obs0[:, 1], atol=1e-5 * obs0[:, 0].max())
+    sim.step(10, -0.02)
+    import torch
+    err = (torch.linalg.vector_norm(sim.psi[0] - psi0) / torch.linalg.vector_norm(psi0)).item()
+    assert err < 1e-4, err
+
+
+def test_1d_4096_250_runs_fp64_full_size(lib):
+    """The paper's production shape: 250 runs of 1D L = 4096 in double precision."""
+    g = (1, (4096,), 0.5, 250)
+    sim = lib.Sim([g], P2, dtype="c128")
+    sim.init_wigner(1006)
+    sim.step(3, 0.01)
+    which = [0, 123, 249]
+    got = sim.psi[0][which].cpu().numpy()
+    ref = oracle_samples(1006, g, P2, 0, which, 3, 0.01)
+    for i, s in enumerate(which):
+        assert rel(got[i], ref[i]) < 1e-12, s

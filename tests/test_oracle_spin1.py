@@ -495,3 +495,13 @@ def test_spin_texture_invariances_and_parseval():
     assert np.allclose(O.spin_texture(rot, g), tex, atol=1e-12)
     bins = O.structure_factor(psi, g)
     assert np.allclose((bins * O.bin_counts(g)).sum(1) / g.sites, tex[:, 1], rtol=1e-12)
+
+
+def test_init_wigner_sample_subset():
+    """Generating selected samples gives exactly those rows of the full set
+    (the counter carries the sample index)."""
+    g = O.Grid(2, (16, 8), 0.5, 4)
+    p = O.Params(1.0, -0.1, 0.09, 1.0, 0.5)
+    full = O.init_wigner(77, g, p, group=1)
+    part = O.init_wigner(77, g, p, group=1, samples=[3, 0])
+    assert np.array_equal(part, full[[3, 0]])
