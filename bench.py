@@ -160,7 +160,7 @@ def adjoint_timing():
     grid = (2, a["n"], 0.5, a["samples"])
     sim = spin1.Sim([grid], a["params"], dtype="c64")
     sim.init_wigner(a["seed"])
-    psi0 = sim.psi[0].clone()
+    psi0 = sim.field_tensor(0).clone()
     sim.step(a["steps"], a["dt"])  # warm up (graphs, tables)
     sim.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

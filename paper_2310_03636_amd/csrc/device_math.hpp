@@ -430,7 +430,8 @@ template <typename Real>
 __device__ __forceinline__ void rotation_coeffs(Real f2, Real theta, Real* s, Real* c) {
   Real sc, ch;
   if constexpr (sizeof(Real) == 4) {
-    sinc_cos_from_square(Real(0.25) * f2 * theta * theta, &sc, &ch);
+    // f2 times a factor that is the same for every site (kept out of site loops)
+    sinc_cos_from_square(f2 * (Real(0.25) * theta * theta), &sc, &ch);
   } else {
     const Real half = Real(0.5) * sqrt(f2) * theta;
     Real sh;
@@ -442,8 +443,8 @@ __device__ __forceinline__ void rotation_coeffs(Real f2, Real theta, Real* s, Re
       sc = sh / half;
     }
   }
-  *s = theta * sc * ch;
-  *c = Real(-0.5) * theta * theta * sc * sc;
+  *s = theta * (sc * ch);
+  *c = (Real(-0.5) * theta * theta) * (sc * sc);
 }
 
 template <typename Real>
@@ -464,7 +465,7 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
   const Real theta = c1 * tau;
   Real s, c, sp, cp;
   rotation_coeffs(f2, theta, &s, &c);
-  angle_sincos(c0 * n * tau, &sp, &cp);
+  angle_sincos(n * (c0 * tau), &sp, &cp);
   Cx<Real> phi[3], chi[3];
   apply_M(psi, phi, g, fz);
   apply_M(phi, chi, g, fz);
@@ -622,7 +623,7 @@ __device__ __forceinline__ void local_update_vjp(const Cx<Real>* psi, const Cx<R
   rotation_coeffs(f2, theta, &s, &c);
   Real s1, s2;
   sigma_coeffs(theta, x, &s1, &s2);
-  angle_sincos(c0 * n * tau, &sp, &cp);
+  angle_sincos(n * (c0 * tau), &sp, &cp);
   // Gt = exp(+i c0 n tau) G'
   Cx<Real> gt[3];
   const Cx<Real> ph = {cp, sp};

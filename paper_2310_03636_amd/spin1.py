@@ -289,7 +289,9 @@ class Sim:
     dtype: "c64" or "c128".  Torch supplies the device memory and a stream
     of its own (default priority); every torch operation of this object runs
     on that stream, so the library's work and torch's copies stay ordered.
-    Methods that return host arrays synchronise that stream.
+    Methods that return host arrays synchronise that stream.  ``psi`` holds
+    the device tensors themselves; work on them from another stream only
+    after ``synchronize()`` (or take them through ``field_tensor``).
     """
 
     def __init__(self, groups, params, dtype="c64", device="cuda:0"):
@@ -357,6 +359,12 @@ class Sim:
 
     def local_update(self, tau):
         local_update(self.ctx, tau)
+
+    def field_tensor(self, group=0):
+        """The device tensor of a group's field once this object's stream has
+        finished its queued work (synchronises)."""
+        self.stream.synchronize()
+        return self.psi[group]
 
     def fields(self):
         """The fields as numpy complex128 arrays (synchronises)."""
@@ -463,7 +471,9 @@ class Sim:
 
 
     def transverse_spin(self, group=0):
-        """F_perp per site of `group` as a device tensor [S, spatial...]."""
+        """F_perp per site of `group` as a device tensor [S, spatial...],
+        enqueued on this object's stream (synchronize() before using it from
+        another stream)."""
         g = self.grids[group]
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((g.samples,) + _spatial(g), dtype=self.psi[group].dtype, device=self.device)

@@ -37,7 +37,7 @@ def test_2d_512_64_samples_full_size(lib):
     sim.autotune(reps=1)
     sim.step(2, 0.02)
     which = [0, 37, 63]
-    got = sim.psi[0][which].cpu().numpy().astype(np.complex128)
+    got = sim.field_tensor(0)[which].cpu().numpy().astype(np.complex128)
     ref = oracle_samples(1002, g, P2, 0, which, 2, 0.02)
     for i, s in enumerate(which):
         assert rel(got[i], ref[i]) < 1e-5, s
@@ -54,7 +54,7 @@ def test_uneven_batch_full_size(lib):
     sim.step(2, 0.02)
     for gi, g in enumerate(groups):
         which = [0, g[3] - 1]
-        got = sim.psi[gi][which].cpu().numpy().astype(np.complex128)
+        got = sim.field_tensor(gi)[which].cpu().numpy().astype(np.complex128)
         ref = oracle_samples(1004, g, P2, gi, which, 2, 0.02)
         for i, s in enumerate(which):
             assert rel(got[i], ref[i]) < 1e-5, (gi, s)
@@ -70,7 +70,7 @@ def test_3d_256_8_samples_full_size_invariants(lib):
     sim = lib.Sim([g], p3, dtype="c64")
     sim.init_wigner(1003)
     sim.autotune(reps=1)
-    psi0 = sim.psi[0].clone()
+    psi0 = sim.field_tensor(0).clone()
     obs0 = sim.observables()
     sim.step(10, 0.02)
     obs1 = sim.observables()
@@ -78,7 +78,7 @@ def test_3d_256_8_samples_full_size_invariants(lib):
     assert np.allclose(obs1[:, 1], obs0[:, 1], atol=1e-5 * obs0[:, 0].max())
     sim.step(10, -0.02)
     import torch
-    err = (torch.linalg.vector_norm(sim.psi[0] - psi0) / torch.linalg.vector_norm(psi0)).item()
+    err = (torch.linalg.vector_norm(sim.field_tensor(0) - psi0) / torch.linalg.vector_norm(psi0)).item()
     assert err < 1e-4, err
 
 
@@ -89,7 +89,7 @@ def test_1d_4096_250_runs_fp64_full_size(lib):
     sim.init_wigner(1006)
     sim.step(3, 0.01)
     which = [0, 123, 249]
-    got = sim.psi[0][which].cpu().numpy()
+    got = sim.field_tensor(0)[which].cpu().numpy()
     ref = oracle_samples(1006, g, P2, 0, which, 3, 0.01)
     for i, s in enumerate(which):
         assert rel(got[i], ref[i]) < 1e-12, s

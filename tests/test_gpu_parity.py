@@ -356,7 +356,9 @@ def test_spin_texture_matches_oracle(lib, grid):
     ref = O.spin_texture(psi0, og)
     for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
         sim = run_gpu(lib, grid, P1, dtype, psi0=psi0)
-        fp = sim.transverse_spin().cpu().numpy()
+        fp_dev = sim.transverse_spin()
+        sim.synchronize()
+        fp = fp_dev.cpu().numpy()
         assert rel(fp, ref_fp) < tol, dtype
         tex = sim.spin_texture()
         assert np.allclose(tex[:, :2], ref[:, :2], rtol=tol), dtype
