@@ -604,3 +604,58 @@ def test_autotune_choices_and_cache(lib, tmp_path):
         lib.set_variant(sim.ctx, 0, 512, 7)
     with pytest.raises(lib.Spin1Error):
         lib.set_variant(sim.ctx, 1, 4096, 0)
+
+
+# ------------------------------------------------------------------ degenerate cases with closed forms
+def _free_gaussian(x, t, x0, s0):
+    """Free Schroedinger evolution of a normalised Gaussian (hbar = m = 1)."""
+    a = 1.0 + 1j * t / s0 ** 2
+    return (np.pi * s0 ** 2) ** -0.25 * a ** -0.5 * np.exp(-((x - x0) ** 2) / (2 * s0 ** 2 * a))
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-11), ("c64", 2e-5)])
+def test_free_gaussian_on_gpu(lib, dtype, tol):
+    """c0 = c1 = q = 0: every component spreads as the free Gaussian, in 1D and
+    as a product in 2D, for any dt (the kinetic step is exact)."""
+    p0 = dict(c0=0.0, c1=0.0, q=0.0, n0=1.0, wigner_var=0.5)
+    x = np.arange(256) * 0.5
+    psi = np.zeros((1, 3, 256), complex)
+    for c in range(3):
+        psi[0, c] = _free_gaussian(x, 0.0, 64.0, 3.0)
+    sim = run_gpu(lib, (1, (256,), 0.5, 1), p0, dtype, psi0=psi, nsteps=40, dt=0.125)
+    ref = _free_gaussian(x, 5.0, 64.0, 3.0)
+    out = sim.fields()[0]
+    for c in range(3):
+        assert np.max(np.abs(out[0, c] - ref)) < tol * 10
+    y = np.arange(128) * 0.5  # box of 64: the tails at the edges stay below 1e-30
+    g2 = np.zeros((1, 3, 128, 256), complex)
+    for c in range(3):
+        g2[0, c] = _free_gaussian(y, 0.0, 32.0, 2.5)[:, None] * _free_gaussian(x, 0.0, 64.0, 3.0)[None, :]
+    sim = run_gpu(lib, (2, (256, 128), 0.5, 1), p0, dtype, psi0=g2, nsteps=20, dt=0.1)
+    ref2 = _free_gaussian(y, 2.0, 32.0, 2.5)[:, None] * _free_gaussian(x, 2.0, 64.0, 3.0)[None, :]
+    out2 = sim.fields()[0]
+    for c in range(3):
+        assert np.max(np.abs(out2[0, c] - ref2)) < tol * 10
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-6)])
+def test_uniform_polar_and_ferromagnet_on_gpu(lib, dtype, tol):
+    """Uniform polar state: psi_0 = sqrt(n) e^{-i c0 n t}; uniform ferromagnet
+    psi_1 = sqrt(n) e^{-i (q + (c0 + c1) n) t}; exact for any dt."""
+    p = dict(c0=1.0, c1=-0.1, q=0.3, n0=1.0, wigner_var=0.5)
+    n = 1.7
+    pol = np.zeros((2, 3, 32, 16), complex)
+    pol[:, 1] = np.sqrt(n)
+    sim = run_gpu(lib, (2, (16, 32), 0.5, 2), p, dtype, psi0=pol, nsteps=15, dt=0.13)
+    out = sim.fields()[0]
+    t = 15 * 0.13
+    assert np.max(np.abs(out[:, 1] - np.sqrt(n) * np.exp(-1j * p["c0"] * n * t))) < tol * 10
+    assert np.max(np.abs(out[:, [0, 2]])) < tol
+    fer = np.zeros((1, 3, 64), complex)
+    fer[:, 0] = np.sqrt(0.8)
+    p2 = dict(c0=1.2, c1=-0.4, q=0.7, n0=1.0, wigner_var=0.5)
+    sim = run_gpu(lib, (1, (64,), 0.5, 1), p2, dtype, psi0=fer, nsteps=6, dt=0.5)
+    ph = np.exp(-1j * (p2["q"] + (p2["c0"] + p2["c1"]) * 0.8) * 3.0)
+    out = sim.fields()[0]
+    assert np.max(np.abs(out[:, 0] - np.sqrt(0.8) * ph)) < tol * 10
+    assert np.max(np.abs(out[:, 1:])) < tol
