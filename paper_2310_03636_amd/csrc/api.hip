@@ -396,11 +396,12 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
   return SPIN1_OK;
 }
 
-int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double dt, double tau_open,
-                       double tau_close) {
-  (void)dt;
+// one step of group G on field (read from src instead when src is given: out of place)
+int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double tau_open, double tau_close,
+                       const void* src = nullptr) {
   XPassArgs xa = xargs(ctx, G);
   xa.psi = field;
+  xa.src = src;
   xa.tau_pre = tau_open;
   xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
   hipError_t e;
@@ -550,7 +551,7 @@ int enqueue_other_groups(spin1_ctx* ctx, const std::vector<char>& in_set, int64_
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
       const GroupState& G = ctx->groups[g];
       if (multi_1d(ctx, G) || in_set[g]) continue;
-      const int rc = enqueue_group_step(ctx, G, G.psi, dt, pre, close);
+      const int rc = enqueue_group_step(ctx, G, G.psi, pre, close);
       if (rc) return rc;
     }
   }
@@ -576,10 +577,12 @@ int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
     ctx->stream = ctx->side;
     rc = enqueue_other_groups(ctx, in_set, n, dt);
     ctx->stream = main;
-    // join even after a failed enqueue, so that a capture stays well formed
     e = hipEventRecord(ctx->join_ev, ctx->side);
-    if (rc) return rc;
-    if (e != hipSuccess) return hip_fail(e, "stream join");
+    if (rc || e != hipSuccess) {
+      // join even after a failed enqueue, so that a capture stays well formed
+      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
+      return rc ? rc : hip_fail(e, "stream join");
+    }
   } else if (others) {
     if ((rc = enqueue_other_groups(ctx, in_set, n, dt))) return rc;
   }
@@ -591,7 +594,7 @@ int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
       if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close);
     if (rc) break;
   }
-  if (overlap) {
+  if (overlap) {  // the main stream waits for the side stream's work, after its own
     const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
     if (!rc && e != hipSuccess) return hip_fail(e, "stream join");
   }
@@ -951,7 +954,7 @@ int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, dou
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
       const GroupState& G = ctx->groups[g];
       rc = int64_t(g) == group ? enqueue_group_step_logged(ctx, G, dt, pre, close, obs_dev + i * S * 3)
-                               : enqueue_group_step(ctx, G, G.psi, dt, pre, close);
+                               : enqueue_group_step(ctx, G, G.psi, pre, close);
       if (rc) return rc;
     }
   }
@@ -1060,27 +1063,29 @@ int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every, const voi
   if ((e = launch_adj_seed(st, ctx->dbl, G.psi, sff, H, g.S, g.sites)) != hipSuccess) return hip_fail(e, "adjoint seed");
   if ((e = hipMemsetAsync(acc, 0, 2 * sizeof(double), st)) != hipSuccess) return hip_fail(e, "clear accumulators");
 
-  // 4. segments in reverse: recompute the states, then walk the steps backwards
+  // 4. segments in reverse: recompute the states, then walk the steps backwards.
+  //    Backwards, the local-update VJPs run at psi_n (closing half of the last
+  //    step), then after each step's kinetic pass at psi_i: the opening half of
+  //    step i fused with the closing half of step i - 1, and at psi_0 the
+  //    opening half alone.
   const int64_t nck = (n + every - 1) / every;
+  const double half = 0.5 * dt;
+  auto local_vjp = [&](int kind, const void* state) -> int {
+    hipError_t le = launch_adj_local(st, ctx->dbl, kind, state, H, g.S, g.sites, half, ctx->p.c0, ctx->p.c1, dt, part);
+    if (le != hipSuccess) return hip_fail(le, "local-update VJP");
+    if ((le = launch_adj_accum(st, part, nblk, acc)) != hipSuccess) return hip_fail(le, "adjoint accumulate");
+    return SPIN1_OK;
+  };
   for (int64_t c = nck - 1; c >= 0; --c) {
     const int64_t len = (n - c * every) < every ? (n - c * every) : every;
     e = hipMemcpyAsync(seg, static_cast<const char*>(ckpt_dev) + size_t(c) * fb, fb, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "segment copy");
-    for (int64_t j = 0; j < len; ++j) {
-      e = hipMemcpyAsync(seg + size_t(j + 1) * fb, seg + size_t(j) * fb, fb, hipMemcpyDeviceToDevice, st);
-      if (e != hipSuccess) return hip_fail(e, "segment copy");
-      if ((rc = enqueue_group_step(ctx, G, seg + size_t(j + 1) * fb, dt, 0.5 * dt, 0.5 * dt))) return rc;
-    }
+    for (int64_t j = 0; j < len; ++j)  // state j + 1 from state j, out of place
+      if ((rc = enqueue_group_step(ctx, G, seg + size_t(j + 1) * fb, half, half, seg + size_t(j) * fb))) return rc;
+    if (c == nck - 1 && (rc = local_vjp(ADJ_CLOSE, seg + size_t(len) * fb))) return rc;
     for (int64_t j = len - 1; j >= 0; --j) {
-      e = launch_adj_local(st, ctx->dbl, true, seg + size_t(j + 1) * fb, H, g.S, g.sites, 0.5 * dt, ctx->p.c0,
-                           ctx->p.c1, dt, part);
-      if (e != hipSuccess) return hip_fail(e, "adjoint closing half");
-      if ((e = launch_adj_accum(st, part, nblk, acc)) != hipSuccess) return hip_fail(e, "adjoint accumulate");
-      if ((rc = enqueue_group_step(ctx, G, H, dt, 0.0, 0.0))) return rc;
-      e = launch_adj_local(st, ctx->dbl, false, seg + size_t(j) * fb, H, g.S, g.sites, 0.5 * dt, ctx->p.c0, ctx->p.c1,
-                           dt, part);
-      if (e != hipSuccess) return hip_fail(e, "adjoint opening half");
-      if ((e = launch_adj_accum(st, part, nblk, acc)) != hipSuccess) return hip_fail(e, "adjoint accumulate");
+      if ((rc = enqueue_group_step(ctx, G, H, 0.0, 0.0))) return rc;
+      if ((rc = local_vjp(c == 0 && j == 0 ? ADJ_OPEN : ADJ_OPEN_CLOSE, seg + size_t(j) * fb))) return rc;
     }
   }
   // 5. outputs in the real-gradient convention

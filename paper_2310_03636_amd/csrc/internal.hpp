@@ -30,6 +30,7 @@ enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3,
 
 struct XPassArgs {
   void* psi;        // field base [S][3][rows][Nx] (STEP, MEASURE, SF*)
+  const void* src;  // STEP: when non-null the field is read from here and written to psi
   void* out;        // SF: complex [S][rows][Nx]; SF_POWER: real [S][rows][Nx]
   double* part;     // MEASURE: [S*rows][4] = (sum n, sum Fz, sum e_loc, sum e_kin_x)
   const void* tw;   // exp(-2 pi i m / Nx)
@@ -118,7 +119,9 @@ hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_
 // reverse mode
 hipError_t launch_fft1_x(hipStream_t st, bool dbl, int n, void* f, const void* tw, int64_t pencils);
 int adj_local_blocks(int S, int64_t sites);
-hipError_t launch_adj_local(hipStream_t st, bool dbl, bool close, const void* state, void* h, int S, int64_t sites,
+// which local-update VJPs k_adj_local applies at the state it is given
+enum AdjLocalKind { ADJ_OPEN = 0, ADJ_CLOSE = 1, ADJ_OPEN_CLOSE = 2 };
+hipError_t launch_adj_local(hipStream_t st, bool dbl, int kind, const void* state, void* h, int S, int64_t sites,
                             double tau, double c0, double c1, double dt, double* part);
 hipError_t launch_adj_accum(hipStream_t st, const double* part, int nblocks, double* acc);
 hipError_t launch_adj_spectrum(hipStream_t st, bool dbl, void* f, const Geom& g, const int32_t* offs, int nbins,

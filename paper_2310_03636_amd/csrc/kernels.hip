@@ -70,13 +70,15 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
   const int64_t row = active ? pid - s * a.rows : 0;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
   const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
-  C* base = static_cast<C*>(a.psi) + s * 3 * a.sites + row * N + t;
+  const int64_t off = s * 3 * a.sites + row * N + t;
+  C* base = static_cast<C*>(a.psi) + off;
+  const C* in = (MODE == MODE_STEP && a.src) ? static_cast<const C*>(a.src) + off : base;
 
   C v[3][R];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int e = 0; e < R; ++e) v[m][e] = active ? base[m * a.sites + e * T] : C{Real(0), Real(0)};
+    for (int e = 0; e < R; ++e) v[m][e] = active ? in[m * a.sites + e * T] : C{Real(0), Real(0)};
 
   if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_LOG) {
     const Real c0 = Real(a.c0), c1 = Real(a.c1);

@@ -231,14 +231,31 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_fft1_x(Cx<Real>* f
   }
 }
 
-// Local-update VJP over a whole field.
+// Local-update VJP over a whole field (tau = dt/2).
 //  CLOSE (backward of a step's closing half): state = psi_{n+1} = R(tau) psi_b;
 //    H in = conj(G) at psi_{n+1}, H out = conj(G) at psi_b; adds
 //    tau Im<G, M psi_{n+1}> to dL/dc1 and dt sum_{m=+-1} Im<G_b, psi_b> to dL/dq.
 //  OPEN (backward of a step's opening half): state = psi_n, psi_a = R(tau) psi_n;
 //    H in = conj(G) at psi_a, H out = conj(G) at psi_n; adds tau Im<G, M psi_a>.
+//  OPEN_CLOSE: the OPEN of step n followed by the CLOSE of step n - 1, both at
+//    state = psi_n (the two halves meet there), in one read and write of H.
 // Per-block FP64 partials (dL/dq, dL/dc1) go to part[2 * blockIdx.x + {0, 1}].
-template <typename Real, bool CLOSE>
+template <typename Real>
+__device__ __forceinline__ void adj_half(const Cx<Real>* pin, const Cx<Real>* pout, const Cx<Real>* gout,
+                                         Cx<Real>* gin, Real tau, Real c0, Real c1, double* dc1) {
+  // dL/dc1 += tau Im<G_out, M psi_out>   (M is the same at input and output)
+  const Cx<Real> g = cmulc(pout[0], pout[1]) + cmulc(pout[1], pout[2]);
+  const Real fz = norm2(pout[0]) - norm2(pout[2]);
+  Cx<Real> mp[3];
+  apply_M(pout, mp, g, fz);
+  double acc = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) acc += double(cmulc(gout[m], mp[m]).im);
+  *dc1 += double(tau) * acc;
+  local_update_vjp(pin, pout, gout, gin, tau, c0, c1);
+}
+
+template <typename Real, int KIND>
 __global__ __launch_bounds__(256) void k_adj_local(const Cx<Real>* __restrict__ state, Cx<Real>* __restrict__ h,
                                                    int S, int64_t sites, Real tau, Real c0, Real c1, double dt,
                                                    double* part) {
@@ -249,45 +266,29 @@ __global__ __launch_bounds__(256) void k_adj_local(const Cx<Real>* __restrict__ 
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t s = i / sites, x = i - s * sites;
     const int64_t o = s * 3 * sites + x;
-    C st[3] = {state[o], state[o + sites], state[o + 2 * sites]};
-    C gout[3] = {conj(h[o]), conj(h[o + sites]), conj(h[o + 2 * sites])};
-    C pin[3], pout[3];
-    if constexpr (CLOSE) {
-      // psi_b = R(-tau) psi_{n+1}
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        pin[m] = st[m];
-        pout[m] = st[m];
-      }
-      local_update(pin, -tau, c0, c1);
-    } else {
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        pin[m] = st[m];
-        pout[m] = st[m];
-      }
+    const C st[3] = {state[o], state[o + sites], state[o + 2 * sites]};
+    C g[3] = {conj(h[o]), conj(h[o + sites]), conj(h[o + 2 * sites])};
+    if constexpr (KIND != ADJ_CLOSE) {
+      // opening half: psi_a = R(tau) psi_n
+      C pout[3] = {st[0], st[1], st[2]}, gin[3];
       local_update(pout, tau, c0, c1);
-    }
-    // dL/dc1 += tau Im<G_out, M psi_out>   (M is the same at input and output)
-    {
-      const Cx<Real> g = cmulc(pout[0], pout[1]) + cmulc(pout[1], pout[2]);
-      const Real fz = norm2(pout[0]) - norm2(pout[2]);
-      C mp[3];
-      apply_M(pout, mp, g, fz);
-      double acc = 0.0;
+      adj_half(st, pout, g, gin, tau, c0, c1, &dc1);
 #pragma unroll
-      for (int m = 0; m < 3; ++m) acc += double(cmulc(gout[m], mp[m]).im);
-      dc1 += double(tau) * acc;
+      for (int m = 0; m < 3; ++m) g[m] = gin[m];
     }
-    C gin[3];
-    local_update_vjp(pin, pout, gout, gin, tau, c0, c1);
-    if constexpr (CLOSE) {
+    if constexpr (KIND != ADJ_OPEN) {
+      // closing half: psi_b = R(-tau) psi_{n+1}
+      C pin[3] = {st[0], st[1], st[2]}, gin[3];
+      local_update(pin, -tau, c0, c1);
+      adj_half(pin, st, g, gin, tau, c0, c1, &dc1);
       // q enters through exp(-i q m^2 dt) on m = +-1 in the step before: dt Im<G_b, psi_b>
       dq += dt * (double(cmulc(gin[0], pin[0]).im) + double(cmulc(gin[2], pin[2]).im));
+#pragma unroll
+      for (int m = 0; m < 3; ++m) g[m] = gin[m];
     }
-    h[o] = conj(gin[0]);
-    h[o + sites] = conj(gin[1]);
-    h[o + 2 * sites] = conj(gin[2]);
+    h[o] = conj(g[0]);
+    h[o + sites] = conj(g[1]);
+    h[o + 2 * sites] = conj(g[2]);
   }
   const double tq = block_sum(dq, scratch);
   const double tc = block_sum(dc1, scratch);
@@ -502,28 +503,30 @@ hipError_t launch_fft1_x(hipStream_t st, bool dbl, int n, void* f, const void* t
 
 int adj_local_blocks(int S, int64_t sites) { return int(grid_for(int64_t(S) * sites, 256)); }
 
-hipError_t launch_adj_local(hipStream_t st, bool dbl, bool close, const void* state, void* h, int S, int64_t sites,
+template <typename Real, int KIND>
+static void adj_local_t(hipStream_t st, unsigned blocks, const void* state, void* h, int S, int64_t sites, double tau,
+                        double c0, double c1, double dt, double* part) {
+  hipLaunchKernelGGL((k_adj_local<Real, KIND>), dim3(blocks), dim3(256), 0, st, static_cast<const Cx<Real>*>(state),
+                     static_cast<Cx<Real>*>(h), S, sites, Real(tau), Real(c0), Real(c1), dt, part);
+}
+
+hipError_t launch_adj_local(hipStream_t st, bool dbl, int kind, const void* state, void* h, int S, int64_t sites,
                             double tau, double c0, double c1, double dt, double* part) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
-  if (dbl) {
-    if (close)
-      hipLaunchKernelGGL((k_adj_local<double, true>), dim3(blocks), dim3(256), 0, st,
-                         static_cast<const Cx<double>*>(state), static_cast<Cx<double>*>(h), S, sites, tau, c0, c1, dt,
-                         part);
+  if (kind != ADJ_OPEN && kind != ADJ_CLOSE && kind != ADJ_OPEN_CLOSE) return hipErrorInvalidValue;
+  auto run = [&](auto tag) {
+    using Real = decltype(tag);
+    if (kind == ADJ_OPEN)
+      adj_local_t<Real, ADJ_OPEN>(st, blocks, state, h, S, sites, tau, c0, c1, dt, part);
+    else if (kind == ADJ_CLOSE)
+      adj_local_t<Real, ADJ_CLOSE>(st, blocks, state, h, S, sites, tau, c0, c1, dt, part);
     else
-      hipLaunchKernelGGL((k_adj_local<double, false>), dim3(blocks), dim3(256), 0, st,
-                         static_cast<const Cx<double>*>(state), static_cast<Cx<double>*>(h), S, sites, tau, c0, c1, dt,
-                         part);
-  } else {
-    if (close)
-      hipLaunchKernelGGL((k_adj_local<float, true>), dim3(blocks), dim3(256), 0, st,
-                         static_cast<const Cx<float>*>(state), static_cast<Cx<float>*>(h), S, sites, float(tau),
-                         float(c0), float(c1), dt, part);
-    else
-      hipLaunchKernelGGL((k_adj_local<float, false>), dim3(blocks), dim3(256), 0, st,
-                         static_cast<const Cx<float>*>(state), static_cast<Cx<float>*>(h), S, sites, float(tau),
-                         float(c0), float(c1), dt, part);
-  }
+      adj_local_t<Real, ADJ_OPEN_CLOSE>(st, blocks, state, h, S, sites, tau, c0, c1, dt, part);
+  };
+  if (dbl)
+    run(double{});
+  else
+    run(float{});
   return hipGetLastError();
 }
 

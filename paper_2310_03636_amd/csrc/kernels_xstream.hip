@@ -49,17 +49,19 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
     __syncthreads();
   }
   C* psi = static_cast<C*>(a.psi);
+  // out of place when a source field of the same layout is given
+  const C* in = a.src ? static_cast<const C*>(a.src) : psi;
   const int64_t npen = int64_t(a.S) * a.rows;
   const Real c0 = Real(a.c0), c1 = Real(a.c1);
   // pencil pid: component m starts at ((s*3 + m) * sites + row * N); rows is a power of two
-  auto comp_base = [&](int64_t pid, int m) -> C* {
+  auto comp_off = [&](int64_t pid, int m) -> int64_t {
     const int64_t s = pid >> a.lg_rows;
-    return psi + (s * 3 + m) * a.sites + (pid & (a.rows - 1)) * N;
+    return (s * 3 + m) * a.sites + (pid & (a.rows - 1)) * N;
   };
   auto load3 = [&](C (&dst)[3][R], int64_t pid) {
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const C* src = comp_base(pid, m);
+      const C* src = in + comp_off(pid, m);
 #pragma unroll
       for (int e = 0; e < R; ++e) dst[m][e] = src[uint32_t(t + e * T)];
     }
@@ -98,7 +100,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
     if (active) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        C* dst = comp_base(pid, m);
+        C* dst = psi + comp_off(pid, m);
 #pragma unroll
         for (int e = 0; e < R; ++e) dst[uint32_t(t + e * T)] = v[m][e];
       }
