@@ -22,6 +22,10 @@ Conventions (readings of the paper where it is silent or ambiguous):
         psi <- R(dt/2) psi;  psi_m <- IFFT[exp(-i(|k|^2/2 + q m^2) dt) FFT psi_m];
         psi <- R(dt/2) psi.
   * ``paper_step`` is the literal Lie-order scheme of Eqs. (3)-(5).
+  * Optional trap potential V(x) (the V_m of Eq. (4), a diagonal term of the
+    operator in Eq. (2)), taken the same for the three components: an array
+    of the spatial shape, or None.  Being a multiple of the identity at each
+    site, it joins the exact local flow: R(tau) = exp(-i tau (V + c0 n + c1 F.f)).
 """
 from dataclasses import dataclass
 import numpy as np
@@ -199,19 +203,20 @@ def init_wigner(seed, grid, p, group=0, samples=None):
 # --------------------------------------------------------------------------
 # sub-steps
 # --------------------------------------------------------------------------
-def local_hamiltonian(psi, c0, c1):
-    """Per-site 3x3 matrix c0 n + c1 F.f; shape [S, spatial..., 3, 3]."""
+def local_hamiltonian(psi, c0, c1, V=None):
+    """Per-site 3x3 matrix V + c0 n + c1 F.f; shape [S, spatial..., 3, 3]."""
     fmats = spin_matrices()
     n = density(psi)
     fvec = spin_vector(psi)
-    h = c0 * n[..., None, None] * np.eye(3)
+    diag = c0 * n if V is None else c0 * n + np.asarray(V, dtype=np.float64)
+    h = diag[..., None, None] * np.eye(3)
     for fa, f in zip(fvec, fmats):
         h = h + c1 * fa[..., None, None] * f
     return h
 
 
-def local_flow(psi, tau, c0, c1, chunk=1 << 18):
-    """Exact flow R(tau) of i d_t psi = (c0 n + c1 F.f) psi at every site.
+def local_flow(psi, tau, c0, c1, chunk=1 << 18, V=None):
+    """Exact flow R(tau) of i d_t psi = (V + c0 n + c1 F.f) psi at every site.
 
     n and F are constants of this local motion, so the flow is the matrix
     exponential exp(-i tau H) of the site matrix H; it is taken from the
@@ -220,7 +225,7 @@ def local_flow(psi, tau, c0, c1, chunk=1 << 18):
     sub-steps in one exact update.
     """
     psi = np.asarray(psi, dtype=np.complex128)
-    h = local_hamiltonian(psi, c0, c1)
+    h = local_hamiltonian(psi, c0, c1, V)
     sv = np.moveaxis(psi, 1, -1)  # [S, spatial..., 3]
     flat_h = h.reshape(-1, 3, 3)
     flat_v = sv.reshape(-1, 3)
@@ -251,18 +256,18 @@ def kinetic_zeeman(psi, dt, q, grid):
     return out
 
 
-def strang_step(psi, dt, p, grid):
+def strang_step(psi, dt, p, grid, V=None):
     """One step of the symmetric split R(dt/2) [K Q](dt) R(dt/2)."""
-    psi = local_flow(psi, 0.5 * dt, p.c0, p.c1)
+    psi = local_flow(psi, 0.5 * dt, p.c0, p.c1, V=V)
     psi = kinetic_zeeman(psi, dt, p.q, grid)
-    psi = local_flow(psi, 0.5 * dt, p.c0, p.c1)
+    psi = local_flow(psi, 0.5 * dt, p.c0, p.c1, V=V)
     return psi
 
 
-def evolve(psi, nsteps, dt, p, grid, step=None):
+def evolve(psi, nsteps, dt, p, grid, step=None, V=None):
     step = strang_step if step is None else step
     for _ in range(nsteps):
-        psi = step(psi, dt, p, grid)
+        psi = step(psi, dt, p, grid) if V is None else step(psi, dt, p, grid, V=V)
     return psi
 
 
@@ -309,8 +314,8 @@ def offdiag_matrix(a, b):
     return s
 
 
-def paper_step(psi, dt, p, grid):
-    """One step of the literal Lie-order scheme of Eqs. (3)-(5), V_m = 0.
+def paper_step(psi, dt, p, grid, V=None):
+    """One step of the literal Lie-order scheme of Eqs. (3)-(5).
 
     (3) kinetic phase exp(-i dt |k|^2/2) in Fourier space;
     (4) diagonal phase exp(-i f_m dt) with f_m the diagonal of the bracket of
@@ -330,7 +335,10 @@ def paper_step(psi, dt, p, grid):
     f_p = q + (c0 + c1) * rho - 2.0 * c1 * dens[:, 2]
     f_0 = (c0 + c1) * rho - c1 * dens[:, 1]
     f_m = q + (c0 + c1) * rho - 2.0 * c1 * dens[:, 0]
-    psi2 = psi1 * np.exp(-1j * np.stack([f_p, f_0, f_m], axis=1) * dt)
+    diag = np.stack([f_p, f_0, f_m], axis=1)
+    if V is not None:  # V_m(x_j) of Eq. (4), the same for every m
+        diag = diag + np.asarray(V, dtype=np.float64)[None, None]
+    psi2 = psi1 * np.exp(-1j * diag * dt)
     a0 = np.conj(psi2[:, 2]) * psi2[:, 1]
     b0 = np.conj(psi2[:, 1]) * psi2[:, 0]
     sv = np.moveaxis(psi2, 1, -1)
@@ -344,11 +352,11 @@ def paper_step(psi, dt, p, grid):
 # --------------------------------------------------------------------------
 # observables (energy functional whose Wirtinger derivative is Eq. (2))
 # --------------------------------------------------------------------------
-def observables(psi, p, grid):
+def observables(psi, p, grid, V=None):
     """Per sample (N, F_z, E) in FP64, array [S, 3].
 
     N = dx^d sum n;  F_z = dx^d sum (|psi_1|^2 - |psi_-1|^2);
-    E = dx^d sum [c0 n^2/2 + c1 |F|^2/2 + q (|psi_1|^2 + |psi_-1|^2)]
+    E = dx^d sum [V n + c0 n^2/2 + c1 |F|^2/2 + q (|psi_1|^2 + |psi_-1|^2)]
         + (dx^d / N_sites) sum_m sum_k |k|^2/2 |FFT psi_m (k)|^2.
     """
     sp_axes = tuple(range(1, 1 + grid.dim))
@@ -357,6 +365,8 @@ def observables(psi, p, grid):
     d1 = np.abs(psi[:, 0]) ** 2
     dm = np.abs(psi[:, 2]) ** 2
     e_loc = 0.5 * p.c0 * n ** 2 + 0.5 * p.c1 * (fx ** 2 + fy ** 2 + fz ** 2) + p.q * (d1 + dm)
+    if V is not None:
+        e_loc = e_loc + np.asarray(V, dtype=np.float64)[None] * n
     k2 = k_squared(grid)
     e_kin = np.zeros(grid.samples)
     for c in range(3):
@@ -442,8 +452,9 @@ def sample_mean_se(bins):
 # --------------------------------------------------------------------------
 # right-hand side of Eq. (2) exactly as printed (for pinning only)
 # --------------------------------------------------------------------------
-def gpe_rhs_printed(psi, p, grid):
-    """i d_t psi from Eq. (2) with the printed matrix, hbar = m = 1.
+def gpe_rhs_printed(psi, p, grid, V=None):
+    """i d_t psi from Eq. (2) with the printed matrix, hbar = m = 1, plus the
+    diagonal potential V (the V_m of Eq. (4)) when given.
 
     The Laplacian is applied spectrally with ``fft_axis``.
     """
@@ -455,6 +466,8 @@ def gpe_rhs_printed(psi, p, grid):
     for c in range(3):
         lap[:, c] = fftn_last(0.5 * k2 * fftn_last(psi[:, c], grid.dim), grid.dim, inverse=True)
     diag = q + (c0 + c1) * rho
+    if V is not None:
+        diag = diag + np.asarray(V, dtype=np.float64)[None]
     out = np.empty_like(psi, dtype=np.complex128)
     out[:, 0] = lap[:, 0] + diag * p1 + c1 * (-2 * np.abs(pm) ** 2 * p1 + np.conj(pm) * p0 * p0)
     # the printed entry c1 (-|psi_0|^2 - q/c1) is expanded so that c1 = 0 is allowed
