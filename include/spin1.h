@@ -117,6 +117,22 @@ SPIN1_API int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid*
 /* Replace the couplings between steps (a quench of q, Sec. 2.1, Fig. 1). */
 SPIN1_API int spin1_set_params(spin1_ctx* ctx, const spin1_params* p);
 
+/* Trap potential V(x) of group `group`: the V_m of Eq. (4), a diagonal term of
+ * the operator of Eq. (2), taken the same for the three components and for
+ * every sample of the group.  v_dev: device array of sites FP64 values in the
+ * field's site order (x fastest), 8-byte aligned; NULL removes the potential.
+ * The library borrows the pointer: the array must stay valid and unchanged
+ * while it is set (until it is replaced, removed, or the context is bound
+ * again, which clears every potential).  Effects: the local update becomes
+ * exp(-i V tau) R(tau) (still exact, since V commutes with the local flow);
+ * the Lie scheme adds V to the diagonal phases of Eq. (4); the energy of
+ * spin1_observables and spin1_step_observed gains dx^d sum V n.  A group with
+ * a potential is stepped one x-pass launch per step (no multi-step 1D kernel,
+ * no grouped x-pass).  Reverse mode returns SPIN1_EUNSUPPORTED while one is
+ * set.  Errors: SPIN1_ESTATE if not bound, SPIN1_EINVAL for a bad group or
+ * misaligned pointer. */
+SPIN1_API int spin1_set_potential(spin1_ctx* ctx, int32_t group, const double* v_dev);
+
 /* Advance every bound group by n steps of dt (dt may be negative): each step
  * is the symmetric split R(dt/2) [K Q](dt) R(dt/2) of the operator of Eq. (2),
  * R the exact local (c0, c1) update (the interaction sub-steps, Eqs. (4)-(5)),

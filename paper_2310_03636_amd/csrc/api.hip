@@ -177,6 +177,7 @@ struct GroupState {
   void* psi;
   Layout lay;
   int nbins;
+  const double* pot = nullptr;  // trap potential [sites] (borrowed), or null
 };
 
 }  // namespace
@@ -332,6 +333,7 @@ int upload_shells(spin1_ctx* ctx, GroupState& G) {
 XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
   XPassArgs a{};
   a.psi = G.psi;
+  a.pot = G.pot;
   a.tw = at(ctx, G.lay.tw[0]);
   a.ph = at(ctx, G.lay.ph[0]);
   a.rows = G.geo.rows;
@@ -389,7 +391,7 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
   if (G.geo.dim > 1 && tau_close != 0.0) {
     {
       Prof pr(ctx, SPIN1_K_LOCAL);
-      e = launch_local(ctx->stream, ctx->dbl, field, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1);
+      e = launch_local(ctx->stream, ctx->dbl, field, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1, G.pot);
     }
     if (e != hipSuccess) return hip_fail(e, "closing local update");
   }
@@ -417,7 +419,7 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
 // steps_per_launch_1d steps, the first opening with R(dt/2), the last closing
 // with R(dt/2), exactly the sequence of the per-step passes.
 int steps_per_launch(const spin1_ctx* ctx, const GroupState& G) {
-  if (G.geo.dim != 1) return 1;
+  if (G.geo.dim != 1 || G.pot) return 1;  // the multi-step kernels take no trap potential
   if (ctx->steps_per_launch_1d > 0) return ctx->steps_per_launch_1d;
   return G.geo.n[0] <= 2048 ? 64 : 1;
 }
@@ -451,7 +453,8 @@ std::vector<size_t> grouped_x_set(const spin1_ctx* ctx) {
   if (!ctx->grouped_x) return out;
   for (size_t g = 0; g < ctx->groups.size() && out.size() < size_t(kMaxGroupedX); ++g) {
     const GroupState& G = ctx->groups[g];
-    if (!multi_1d(ctx, G) && G.geo.n[0] >= 16 && G.geo.n[0] <= grouped_x_max_n(ctx->dbl)) out.push_back(g);
+    if (!multi_1d(ctx, G) && !G.pot && G.geo.n[0] >= 16 && G.geo.n[0] <= grouped_x_max_n(ctx->dbl))
+      out.push_back(g);
   }
   if (out.size() < 2) out.clear();
   return out;
@@ -510,7 +513,7 @@ int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
         {
           Prof pr(ctx, SPIN1_K_LOCAL);
           e = launch_paper_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, dt, ctx->p.c0, ctx->p.c1,
-                                 ctx->p.q);
+                                 ctx->p.q, G.pot);
         }
         if (e != hipSuccess) return hip_fail(e, "Lie-scheme local pass");
       }
@@ -801,7 +804,7 @@ int spin1_local_update(spin1_ctx* ctx, double tau) {
   if (!isfinite(tau)) return fail(SPIN1_EINVAL, "tau must be finite");
   for (auto& G : ctx->groups) {
     Prof pr(ctx, SPIN1_K_LOCAL);
-    const hipError_t e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau, ctx->p.c0, ctx->p.c1);
+    const hipError_t e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau, ctx->p.c0, ctx->p.c1, G.pot);
     if (e != hipSuccess) return hip_fail(e, "local update");
   }
   return SPIN1_OK;
@@ -929,7 +932,7 @@ static int enqueue_group_step_logged(spin1_ctx* ctx, const GroupState& G, double
   if (G.geo.dim > 1 && tau_close != 0.0) {
     {
       Prof pr(ctx, SPIN1_K_LOCAL);
-      e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1);
+      e = launch_local(ctx->stream, ctx->dbl, G.psi, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1, G.pot);
     }
     if (e != hipSuccess) return hip_fail(e, "closing local update");
   }
@@ -994,6 +997,7 @@ static int check_adjoint_args(spin1_ctx* ctx, int64_t n, double dt, int64_t ever
   if (rc) return rc;
   if (ctx->groups.size() != 1) return fail(SPIN1_EUNSUPPORTED, "reverse mode supports one bound group");
   if (ctx->scheme != SPIN1_SCHEME_STRANG) return fail(SPIN1_EUNSUPPORTED, "reverse mode takes the Strang scheme");
+  if (ctx->groups[0].pot) return fail(SPIN1_EUNSUPPORTED, "reverse mode takes no trap potential");
   if (n < 1) return fail(SPIN1_EINVAL, "n must be >= 1");
   if (every < 1) return fail(SPIN1_EINVAL, "checkpoint interval must be >= 1");
   if (!isfinite(dt) || dt == 0.0) return fail(SPIN1_EINVAL, "dt must be finite and nonzero");
@@ -1200,6 +1204,17 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
       ctx->variant[pass][ctx->dbl ? 1 : 0][lg] = int8_t(best);
     }
   ctx->version++;
+  return SPIN1_OK;
+}
+
+int spin1_set_potential(spin1_ctx* ctx, int32_t group, const double* v_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (reinterpret_cast<uintptr_t>(v_dev) % sizeof(double))
+    return fail(SPIN1_EINVAL, "the potential must be aligned to 8 bytes");
+  ctx->groups[size_t(group)].pot = v_dev;
+  ctx->version++;  // captured graphs hold the old kernel arguments and launch pattern
   return SPIN1_OK;
 }
 

@@ -455,6 +455,20 @@ __device__ __forceinline__ void angle_sincos(Real a, Real* sn, Real* cs) {
     sincos(a, sn, cs);
 }
 
+// The phase angle V tau of a trap potential for a kernel in precision Real:
+// reduced to [-pi, pi] in FP64 first, so that its single-precision rounding
+// stays ~1e-7 rad however deep the trap
+template <typename Real>
+__device__ __forceinline__ Real pot_angle(double v, double tau) {
+  const double a = v * tau;
+  if constexpr (sizeof(Real) == 8) {
+    return a;
+  } else {
+    constexpr double kTwoPi = 6.283185307179586476925;
+    return Real(a - kTwoPi * rint(a * (1.0 / kTwoPi)));
+  }
+}
+
 template <typename Real>
 __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, Real c1) {
   const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
@@ -492,8 +506,21 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
 //      c = (cos x - 1)/lambda^2, x = lambda theta (same coefficients as the
 //      exact rotation, from the half-angle sinc).
 // ---------------------------------------------------------------------------
+// exp(-i V tau) on the three components of a site: the trap potential V is a
+// multiple of the identity, so it commutes with the local flow and joins it
+// exactly as this extra phase (vtau from pot_angle)
 template <typename Real>
-__device__ __forceinline__ void paper_local_update(Cx<Real>* psi, Real dt, Real c0, Real c1, Real q) {
+__device__ __forceinline__ void potential_phase(Cx<Real>* psi, Real vtau) {
+  Real sn, cs;
+  angle_sincos(vtau, &sn, &cs);
+  const Cx<Real> ph = {cs, -sn};
+#pragma unroll
+  for (int m = 0; m < 3; ++m) psi[m] = ph * psi[m];
+}
+
+template <typename Real>
+__device__ __forceinline__ void paper_local_update(Cx<Real>* psi, Real dt, Real c0, Real c1, Real q,
+                                                   Real vdt = Real(0)) {
   const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
   const Real n = d1 + d0 + dm;
   const Real base = (c0 + c1) * n;
@@ -501,7 +528,7 @@ __device__ __forceinline__ void paper_local_update(Cx<Real>* psi, Real dt, Real 
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     Real sn, cs;
-    angle_sincos(f[m] * dt, &sn, &cs);
+    angle_sincos(f[m] * dt + vdt, &sn, &cs);  // vdt = V dt, the V_m of Eq. (4)
     psi[m] = psi[m] * Cx<Real>{cs, -sn};
   }
   const Real theta = c1 * dt;

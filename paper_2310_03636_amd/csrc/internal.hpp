@@ -31,6 +31,7 @@ enum PassMode { MODE_STEP = 0, MODE_MEASURE = 1, MODE_SF = 2, MODE_SF_POWER = 3,
 struct XPassArgs {
   void* psi;        // field base [S][3][rows][Nx] (STEP, MEASURE, SF*)
   const void* src;  // STEP: when non-null the field is read from here and written to psi
+  const double* pot;  // trap potential V [rows][Nx] of the group (same for every sample), or null
   void* out;        // SF: complex [S][rows][Nx]; SF_POWER: real [S][rows][Nx]
   double* part;     // MEASURE: [S*rows][4] = (sum n, sum Fz, sum e_loc, sum e_kin_x)
   const void* tw;   // exp(-2 pi i m / Nx)
@@ -102,7 +103,9 @@ hipError_t launch_xpass_grouped(hipStream_t st, bool dbl, const XGroupArgs& a);
 // thread group holding all three components
 hipError_t launch_x1d_multi(hipStream_t st, bool dbl, int n, const XPassArgs& a, int K, double dt, bool open_half,
                             bool close_half, bool split);
-hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1);
+// pot: trap potential [sites] or null
+hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1,
+                        const double* pot);
 // F_perp per site [S][sites] (field precision)
 hipError_t launch_f_perp(hipStream_t st, bool dbl, const void* psi, int S, int64_t sites, void* out);
 // per sample (mean |F_perp|, mean |F_perp|^2, Larmor-phase winding along x); part: S*rows*3 doubles
@@ -110,7 +113,7 @@ hipError_t launch_texture(hipStream_t st, bool dbl, const void* psi, int S, int6
                           double* part, double* out);
 // the paper's local sub-steps (4)-(5) over dt at every site
 hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double dt, double c0,
-                              double c1, double q);
+                              double c1, double q, const double* pot);
 hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_t sites, const int32_t* perm,
                       const int32_t* offs, int nbins, double* out);
 hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,

@@ -80,24 +80,17 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
 #pragma unroll
     for (int e = 0; e < R; ++e) v[m][e] = active ? in[m * a.sites + e * T] : C{Real(0), Real(0)};
 
+  // trap potential of this pencil's row (x = t + e*T), or null
+  const double* prow = a.pot ? a.pot + row * N : nullptr;
   if constexpr (MODE == MODE_STEP || MODE == MODE_STEP_LOG) {
     const Real c0 = Real(a.c0), c1 = Real(a.c1);
-    if (a.tau_pre != 0.0) {
-      const Real tau = Real(a.tau_pre);
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        C site[3] = {v[0][e], v[1][e], v[2][e]};
-        local_update(site, tau, c0, c1);
-        v[0][e] = site[0];
-        v[1][e] = site[1];
-        v[2][e] = site[2];
-      }
-    }
+    if (a.tau_pre != 0.0) local_update_sites<Real, R, T, POT_IF_SET>(v, t, Real(a.tau_pre), c0, c1, prow, a.tau_pre);
     const TabEntry<Real>* ph = static_cast<const TabEntry<Real>*>(a.ph);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (MODE == MODE_STEP_LOG) {
 #pragma unroll
-      for (int e = 0; e < R; ++e) site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc);
+      for (int e = 0; e < R; ++e)
+        site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc, prow ? prow[t + e * T] : 0.0);
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         fft_pencil<Real, N, R>(v[m], t, L, tw);
@@ -116,17 +109,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
 #pragma unroll
       for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
     }
-    if (a.tau_post != 0.0) {
-      const Real tau = Real(a.tau_post);
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        C site[3] = {v[0][e], v[1][e], v[2][e]};
-        local_update(site, tau, c0, c1);
-        v[0][e] = site[0];
-        v[1][e] = site[1];
-        v[2][e] = site[2];
-      }
-    }
+    if (a.tau_post != 0.0) local_update_sites<Real, R, T, POT_IF_SET>(v, t, Real(a.tau_post), c0, c1, prow, a.tau_post);
     if (active) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
@@ -136,22 +119,22 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
     if constexpr (MODE == MODE_STEP_LOG) pencil_sums_out<T>(acc, lds, p, t, active, a.part + pid * 4);
   } else if constexpr (MODE == MODE_PAPER) {
     const Real c0 = Real(a.c0), c1 = Real(a.c1), q = Real(a.q);
-    auto local_all = [&](Real dt) {
+    auto local_all = [&](double dt) {
 #pragma unroll
       for (int e = 0; e < R; ++e) {
         C site[3] = {v[0][e], v[1][e], v[2][e]};
-        paper_local_update(site, dt, c0, c1, q);
+        paper_local_update(site, Real(dt), c0, c1, q, prow ? pot_angle<Real>(prow[t + e * T], dt) : Real(0));
         v[0][e] = site[0];
         v[1][e] = site[1];
         v[2][e] = site[2];
       }
     };
-    if (a.tau_pre != 0.0) local_all(Real(a.tau_pre));
+    if (a.tau_pre != 0.0) local_all(a.tau_pre);
     // kinetic phase alone (the m = 0 row of the x table; q sits in D)
     const TabEntry<Real>* ph0 = static_cast<const TabEntry<Real>*>(a.ph) + N;
 #pragma unroll
     for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph0);
-    if (a.tau_post != 0.0) local_all(Real(a.tau_post));
+    if (a.tau_post != 0.0) local_all(a.tau_post);
     if (active) {
 #pragma unroll
       for (int m = 0; m < 3; ++m)
@@ -161,7 +144,8 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
   } else if constexpr (MODE == MODE_MEASURE) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int e = 0; e < R; ++e) site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc);
+    for (int e = 0; e < R; ++e)
+      site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc, prow ? prow[t + e * T] : 0.0);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       fft_pencil<Real, N, R>(v[m], t, L, tw);

@@ -6,16 +6,19 @@
 namespace spin1 {
 
 // --------------------------------------------------------------------------
-// local update alone (closing half step of multi-dimensional grids)
+// local update alone (closing half step of multi-dimensional grids); pot: the
+// trap potential [sites] or null
 // --------------------------------------------------------------------------
 template <typename Real>
-__global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sites, Real tau, Real c0, Real c1) {
+__global__ __launch_bounds__(256) void k_local(Cx<Real>* psi, int S, int64_t sites, Real tau, Real c0, Real c1,
+                                               const double* pot, double tau_d) {
   const int64_t total = int64_t(S) * sites;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t s = i / sites, x = i - s * sites;
     Cx<Real>* b = psi + s * 3 * sites + x;
     Cx<Real> site[3] = {b[0], b[sites], b[2 * sites]};
     local_update(site, tau, c0, c1);
+    if (pot) potential_phase(site, pot_angle<Real>(pot[x], tau_d));
     b[0] = site[0];
     b[sites] = site[1];
     b[2 * sites] = site[2];
@@ -88,13 +91,13 @@ __global__ __launch_bounds__(256) void k_texture_finish(const double* part, int6
 
 template <typename Real>
 __global__ __launch_bounds__(256) void k_paper_local(Cx<Real>* psi, int S, int64_t sites, Real dt, Real c0, Real c1,
-                                                     Real q) {
+                                                     Real q, const double* pot, double dt_d) {
   const int64_t total = int64_t(S) * sites;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t s = i / sites, x = i - s * sites;
     Cx<Real>* b = psi + s * 3 * sites + x;
     Cx<Real> site[3] = {b[0], b[sites], b[2 * sites]};
-    paper_local_update(site, dt, c0, c1, q);
+    paper_local_update(site, dt, c0, c1, q, pot ? pot_angle<Real>(pot[x], dt_d) : Real(0));
     b[0] = site[0];
     b[sites] = site[1];
     b[2 * sites] = site[2];
@@ -402,26 +405,27 @@ hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint6
   return hipGetLastError();
 }
 
-hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1) {
+hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double tau, double c0, double c1,
+                        const double* pot) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
     hipLaunchKernelGGL(k_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites, tau,
-                       c0, c1);
+                       c0, c1, pot, tau);
   else
     hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
-                       float(tau), float(c0), float(c1));
+                       float(tau), float(c0), float(c1), pot, tau);
   return hipGetLastError();
 }
 
 hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_t sites, double dt, double c0,
-                              double c1, double q) {
+                              double c1, double q, const double* pot) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
     hipLaunchKernelGGL(k_paper_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites,
-                       dt, c0, c1, q);
+                       dt, c0, c1, q, pot, dt);
   else
     hipLaunchKernelGGL(k_paper_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
-                       float(dt), float(c0), float(c1), float(q));
+                       float(dt), float(c0), float(c1), float(q), pot, dt);
   return hipGetLastError();
 }
 

@@ -20,7 +20,9 @@ namespace spin1 {
 // PLAIN: the stage twiddles rounded once to plain complex values (FP32 only):
 // half the multiply cost and LDS of the hi+lo form, at a larger systematic
 // rounding of the transform (see the precision option in spin1.h)
-template <typename Real, int N, int V, bool PLAIN, bool ENABLED = XCfg<N, Real, V>::STREAM>
+// POT: the group has a trap potential (a separate instantiation, so that the
+// common case keeps its register budget)
+template <typename Real, int N, int V, bool PLAIN, bool POT = false, bool ENABLED = XCfg<N, Real, V>::STREAM>
 __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
  if constexpr (ENABLED) {
   using C = Cx<Real>;
@@ -72,31 +74,20 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
     const int64_t pid = g * P + p;
     const bool active = pid < npen;
     C v[3][R];
-    if (active) load3(v, pid);
-    if (a.tau_pre != 0.0) {
-      const Real tau = Real(a.tau_pre);
+    if (active) {
+      load3(v, pid);
+    } else {  // a pencil past the end: defined values, never stored
 #pragma unroll
-      for (int e = 0; e < R; ++e) {
-        C site[3] = {v[0][e], v[1][e], v[2][e]};
-        local_update(site, tau, c0, c1);
-        v[0][e] = site[0];
-        v[1][e] = site[1];
-        v[2][e] = site[2];
-      }
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int e = 0; e < R; ++e) v[m][e] = C{Real(0), Real(0)};
     }
+    const double* prow = POT ? a.pot + (pid & (a.rows - 1)) * N : nullptr;
+    if (a.tau_pre != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_pre), c0, c1, prow, a.tau_pre);
 #pragma unroll
     for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, TWA{stw}, ph + (m == 1 ? N : 0));
-    if (a.tau_post != 0.0) {
-      const Real tau = Real(a.tau_post);
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        C site[3] = {v[0][e], v[1][e], v[2][e]};
-        local_update(site, tau, c0, c1);
-        v[0][e] = site[0];
-        v[1][e] = site[1];
-        v[2][e] = site[2];
-      }
-    }
+    if (a.tau_post != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_post), c0, c1, prow,
+                                                                           a.tau_post);
     if (active) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
@@ -112,15 +103,15 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
-template <typename Real, int N, int V, bool PLAIN>
+template <typename Real, int N, int V, bool PLAIN, bool POT = false>
 static hipError_t xpass_stream_v(hipStream_t st, const XPassArgs& a) {
   constexpr int P = XCfg<N, Real, V>::P;
   const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
   XPassArgs b = a;
   b.lg_rows = ilog2(a.rows);
-  const int64_t grid = stream_grid(k_xpass_stream<Real, N, V, PLAIN>, XCfg<N, Real, V>::THREADS, blocks);
-  hipLaunchKernelGGL((k_xpass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS), 0,
-                     st, b, blocks);
+  const int64_t grid = stream_grid(k_xpass_stream<Real, N, V, PLAIN, POT>, XCfg<N, Real, V>::THREADS, blocks);
+  hipLaunchKernelGGL((k_xpass_stream<Real, N, V, PLAIN, POT>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS),
+                     0, st, b, blocks);
   return hipGetLastError();
 }
 
@@ -136,6 +127,8 @@ static hipError_t xpass_stream_p(hipStream_t st, const XPassArgs& a, int v) {
 template <typename Real, int N>
 static hipError_t xstream_n(hipStream_t st, const XPassArgs& a, int variant) {
   if constexpr (XCfg<N, Real>::STREAM) {
+    // a group with a trap potential runs the default variant
+    if (a.pot) return xpass_stream_v<Real, N, 0, false, true>(st, a);
     if constexpr (sizeof(Real) == 4)
       if (variant >= kPlainTwiddles) return xpass_stream_p<Real, N, true>(st, a, variant - kPlainTwiddles);
     return xpass_stream_p<Real, N, false>(st, a, variant % kPlainTwiddles);

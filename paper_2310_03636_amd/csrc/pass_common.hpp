@@ -107,6 +107,27 @@ __device__ __forceinline__ int signed_k(int k) {
   return k < N / 2 ? k : k - N;
 }
 
+// Local update R(tau) of the R sites held by thread t of a pencil (element e
+// at x = t + e*T), followed by exp(-i V tau) with V from prow, the trap
+// potential of the pencil's row: POT_NEVER, POT_ALWAYS (prow valid), or
+// POT_IF_SET (when prow is not null).
+enum { POT_NEVER = 0, POT_ALWAYS = 1, POT_IF_SET = 2 };
+template <typename Real, int R, int T, int POT = POT_NEVER>
+__device__ __forceinline__ void local_update_sites(Cx<Real> (&v)[3][R], int t, Real tau, Real c0, Real c1,
+                                                   const double* prow = nullptr, double tau_d = 0.0) {
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    Cx<Real> site[3] = {v[0][e], v[1][e], v[2][e]};
+    local_update(site, tau, c0, c1);
+    if constexpr (POT == POT_ALWAYS) potential_phase(site, pot_angle<Real>(prow[t + e * T], tau_d));
+    if constexpr (POT == POT_IF_SET)
+      if (prow) potential_phase(site, pot_angle<Real>(prow[t + e * T], tau_d));
+    v[0][e] = site[0];
+    v[1][e] = site[1];
+    v[2][e] = site[2];
+  }
+}
+
 // sum over the T consecutive lanes of a pencil (T a power of two <= 64)
 template <int T>
 __device__ __forceinline__ double lane_group_sum(double v) {
@@ -133,10 +154,11 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 }
 
 // FP64 site sums of the observables: n, F_z and the local energy density
-// c0/2 n^2 + c1/2 |F|^2 + q (|psi_1|^2 + |psi_-1|^2) (acc[0..2])
+// V n + c0/2 n^2 + c1/2 |F|^2 + q (|psi_1|^2 + |psi_-1|^2) (acc[0..2]), V the trap
+// potential at the site (0 without one)
 template <typename Real>
 __device__ __forceinline__ void site_sums(Cx<Real> p1, Cx<Real> p0, Cx<Real> pm, double c0, double c1, double q,
-                                          double* acc) {
+                                          double* acc, double v = 0.0) {
   const double d1 = double(norm2(p1)), d0 = double(norm2(p0)), dm = double(norm2(pm));
   const Cx<Real> g = cmulc(p1, p0) + cmulc(p0, pm);
   const double gre = double(g.re), gim = double(g.im);
@@ -144,7 +166,7 @@ __device__ __forceinline__ void site_sums(Cx<Real> p1, Cx<Real> p0, Cx<Real> pm,
   const double f2 = 2.0 * (gre * gre + gim * gim) + fz * fz;
   acc[0] += n;
   acc[1] += fz;
-  acc[2] += 0.5 * c0 * n * n + 0.5 * c1 * f2 + q * (d1 + dm);
+  acc[2] += v * n + 0.5 * c0 * n * n + 0.5 * c1 * f2 + q * (d1 + dm);
 }
 
 // Sum acc[0..3] over the T threads of pencil p and write the four totals to

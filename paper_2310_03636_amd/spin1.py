@@ -23,7 +23,7 @@ OK, EINVAL, EUNSUPPORTED, EHIP, ESTATE, ENOMEM = 0, -1, -2, -3, -4, -5
 FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
-    "spin1_init_wigner", "spin1_set_params", "spin1_step", "spin1_structure_factor",
+    "spin1_init_wigner", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_structure_factor",
     "spin1_observables", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
     "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
@@ -81,6 +81,7 @@ def load():
         "spin1_bind": (ctypes.c_int, [vp, gp, i32, pp, ctypes.POINTER(vp), vp]),
         "spin1_init_wigner": (ctypes.c_int, [vp, ctypes.c_uint64, gp, i32, pp, ctypes.POINTER(vp), vp]),
         "spin1_set_params": (ctypes.c_int, [vp, pp]),
+        "spin1_set_potential": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step": (ctypes.c_int, [vp, i64, f64]),
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
@@ -195,6 +196,11 @@ def init_wigner(ctx, seed, grids, params, psi_ptrs, workspace_ptr):
 
 def set_params(ctx, params):
     _check(load().spin1_set_params(ctx, ctypes.byref(params)))
+
+
+def set_potential(ctx, group, v_ptr):
+    """v_ptr: device address of sites FP64 values, or 0 to remove the potential."""
+    _check(load().spin1_set_potential(ctx, int(group), ctypes.c_void_p(int(v_ptr)) if v_ptr else None))
 
 
 def step(ctx, n, dt):
@@ -314,6 +320,7 @@ class Sim:
         self.ctx = create(self.dtype_code, self.stream.cuda_stream)
         self.nbins = [num_bins(g) for g in self.grids]
         self.bound = False
+        self.potentials = {}  # group -> FP64 device tensor (the library borrows it)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -333,9 +340,32 @@ class Sim:
     def synchronize(self):
         self.stream.synchronize()
 
+    def _rebind_potentials(self):
+        for group, v in self.potentials.items():
+            set_potential(self.ctx, group, v.data_ptr())
+
     def init_wigner(self, seed):
         init_wigner(self.ctx, seed, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
         self.bound = True
+        self._rebind_potentials()
+
+    def set_potential(self, group, V):
+        """Trap potential V(x) of a group (array of the spatial shape, the same
+        for every component and sample), or None to remove it.  Applies from
+        the next step; kept across init_wigner / set_fields."""
+        torch = self.torch
+        if V is None:
+            self.potentials.pop(group, None)
+            if self.bound:
+                set_potential(self.ctx, group, 0)
+            return
+        shape = _spatial(self.grids[group])
+        with torch.cuda.stream(self.stream):
+            v = torch.as_tensor(np.asarray(V, dtype=np.float64) if not isinstance(V, torch.Tensor) else V)
+            v = v.to(device=self.device, dtype=torch.float64).reshape(shape).contiguous()
+        self.potentials[group] = v
+        if self.bound:
+            set_potential(self.ctx, group, v.data_ptr())
 
     def set_fields(self, fields):
         """Copy host or device arrays into the fields and bind them."""
@@ -346,6 +376,7 @@ class Sim:
                 dst.copy_(src_t.to(self.cdtype).reshape(dst.shape))
         bind(self.ctx, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
         self.bound = True
+        self._rebind_potentials()
 
     def set_params(self, params):
         self.params = params if isinstance(params, Params) else make_params(**params)
