@@ -177,7 +177,7 @@ SPIN1_API int spin1_spin_texture(spin1_ctx* ctx, int32_t group, double* out_dev)
 SPIN1_API int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, double* obs_dev);
 
 /* Apply the exact local update R(tau) alone to every bound field (Eqs. (4)-(5)
- * combined, q excluded). */
+ * combined, q excluded; with exp(-i V tau) where a trap potential is set). */
 SPIN1_API int spin1_local_update(spin1_ctx* ctx, double tau);
 
 /* Reverse mode (one bound group).  The caller owns a checkpoint array of
