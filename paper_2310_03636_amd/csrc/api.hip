@@ -377,11 +377,19 @@ int variant_of(spin1_ctx* ctx, int pass, int n) {
   return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)] + twiddle_offset(ctx);
 }
 
-// the passes of a step after the x-pass: y/z passes, closing half step (2D/3D)
-int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double tau_close) {
+// Direction of the streaming step pass with index k in the sequence of passes
+// (dim per step): every other pass walks its work items backwards, so that it
+// starts on the data the pass before it wrote last (still in the last-level
+// cache).
+int pass_reverse(int64_t k) { return int(k & 1); }
+
+// the passes of a step after the x-pass: y/z passes, closing half step (2D/3D);
+// step: index of the step in the call (sets the pass directions)
+int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double tau_close, int64_t step = 0) {
   hipError_t e;
   for (int a = 1; a < G.geo.dim; ++a) {
-    const SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
+    SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
+    sa.reverse = pass_reverse(step * G.geo.dim + a);
     {
       Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
       e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa, variant_of(ctx, 1, G.geo.n[a]));
@@ -398,12 +406,14 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
   return SPIN1_OK;
 }
 
-// one step of group G on field (read from src instead when src is given: out of place)
+// one step of group G on field (read from src instead when src is given: out of
+// place); step: index of the step in the call (sets the pass directions)
 int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double tau_open, double tau_close,
-                       const void* src = nullptr) {
+                       const void* src = nullptr, int64_t step = 0) {
   XPassArgs xa = xargs(ctx, G);
   xa.psi = field;
   xa.src = src;
+  xa.reverse = pass_reverse(step * G.geo.dim);
   xa.tau_pre = tau_open;
   xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
   hipError_t e;
@@ -412,7 +422,7 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
     e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, variant_of(ctx, 0, G.geo.n[0]));
   }
   if (e != hipSuccess) return hip_fail(e, "x-pass");
-  return enqueue_group_rest(ctx, G, field, tau_close);
+  return enqueue_group_rest(ctx, G, field, tau_close, step);
 }
 
 // 1D groups with more than one step per launch: consecutive chunks of up to
@@ -507,7 +517,7 @@ int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
         e = launch_xpass(ctx->stream, ctx->dbl, MODE_PAPER, G.geo.n[0], xa);
       }
       if (e != hipSuccess) return hip_fail(e, "Lie-scheme x-pass");
-      const int rc = enqueue_group_rest(ctx, G, G.psi, 0.0);
+      const int rc = enqueue_group_rest(ctx, G, G.psi, 0.0, i);
       if (rc) return rc;
       if (G.geo.dim > 1 && i == n - 1) {
         {
@@ -554,7 +564,7 @@ int enqueue_other_groups(spin1_ctx* ctx, const std::vector<char>& in_set, int64_
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
       const GroupState& G = ctx->groups[g];
       if (multi_1d(ctx, G) || in_set[g]) continue;
-      const int rc = enqueue_group_step(ctx, G, G.psi, pre, close);
+      const int rc = enqueue_group_step(ctx, G, G.psi, pre, close, nullptr, i);
       if (rc) return rc;
     }
   }
@@ -594,7 +604,7 @@ int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
     const double close = i == n - 1 ? 0.5 * dt : 0.0;
     rc = enqueue_grouped_x(ctx, set, pre, close);
     for (size_t g : set)
-      if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close);
+      if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close, i);
     if (rc) break;
   }
   if (overlap) {  // the main stream waits for the side stream's work, after its own
@@ -957,7 +967,7 @@ int spin1_step_observed(spin1_ctx* ctx, int64_t n, double dt, int32_t group, dou
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
       const GroupState& G = ctx->groups[g];
       rc = int64_t(g) == group ? enqueue_group_step_logged(ctx, G, dt, pre, close, obs_dev + i * S * 3)
-                               : enqueue_group_step(ctx, G, G.psi, pre, close);
+                               : enqueue_group_step(ctx, G, G.psi, pre, close, nullptr, i);
       if (rc) return rc;
     }
   }

@@ -43,6 +43,7 @@ struct XPassArgs {
   double kscale;    // 2 pi / (Nx dx)
   double power_scale;  // SF_POWER: 1 / N_sites
   int lg_rows;      // log2(rows), set by the launcher
+  int reverse;      // STEP (streaming kernel): walk the work items from the last one
 };
 
 // One x-pass launch over the step passes of several groups (pencil lengths
@@ -80,6 +81,7 @@ struct SPassArgs {
   double kscale;
   double power_scale;
   int lg_tiles, lg_outer;  // log2 of (inner / TX) and of outer, set by the launcher
+  int reverse;      // STEP (streaming kernel): walk the work items from the last one
 };
 
 hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,

@@ -13,6 +13,9 @@ namespace spin1 {
 // pre-pass state.  The x-pass does not: without the second register set it
 // fits three wavefronts per SIMD instead of two, and the other wavefronts
 // cover its loads (measured 4-6% faster on 256- and 512-point pencils).
+// Consecutive passes walk the items in opposite directions (the host sets
+// `reverse` on every other pass), so each pass starts on the data the one
+// before it wrote last, which the last-level cache still holds.
 // --------------------------------------------------------------------------
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
@@ -46,6 +49,7 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
   const uint32_t lane_off = uint32_t((c + int64_t(t) * a.sa) * int64_t(sizeof(C)));
   const uint32_t step_e = uint32_t(int64_t(T) * a.sa * int64_t(sizeof(C)));
   auto tile_base = [&](int64_t item) -> char* {
+    if (a.reverse) item = items - 1 - item;
     const int64_t tile = item & (tiles - 1);
     const int64_t rest = item >> a.lg_tiles;
     const int64_t o = rest & (a.outer - 1), f = rest >> a.lg_outer;

@@ -13,6 +13,9 @@ namespace spin1 {
 // pre-pass state.  The x-pass does not: without the second register set it
 // fits three wavefronts per SIMD instead of two, and the other wavefronts
 // cover its loads (measured 4-6% faster on 256- and 512-point pencils).
+// Consecutive passes walk the items in opposite directions (the host sets
+// `reverse` on every other pass), so each pass starts on the data the one
+// before it wrote last, which the last-level cache still holds.
 // --------------------------------------------------------------------------
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
@@ -71,7 +74,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   int64_t g = blockIdx.x;
   if (g >= groups) return;
   for (; g < groups; g += gridDim.x) {
-    const int64_t pid = g * P + p;
+    const int64_t pid = (a.reverse ? groups - 1 - g : g) * P + p;
     const bool active = pid < npen;
     C v[3][R];
     if (active) {
