@@ -168,7 +168,9 @@ k_xpass_grouped(XGroupArgs a) {
 // --------------------------------------------------------------------------
 template <int N, typename Real>
 struct MultiCfg {
-  static constexpr int R = XCfg<N, Real>::R;
+  // radix 8 at every length: at Nx = 4096 it keeps 3 x 8 values per thread
+  // (512 threads), where radix 16 needs more registers than a thread has
+  static constexpr int R = N <= 8 ? N : 8;
   static constexpr int T = N / R;
   static constexpr bool HALF_TW = N >= 4096;
   static constexpr int TW_N = HALF_TW ? N / 2 + 1 : N;
