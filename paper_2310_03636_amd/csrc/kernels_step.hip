@@ -10,16 +10,20 @@ namespace spin1 {
 // holds the same 3 x 8 values whatever the group; a workgroup of 256 threads
 // runs P = 2048 / N pencils of N / 8 threads.  The workgroup walks the
 // concatenated item list with a stride of gridDim.x; items of one group are
-// contiguous, so it reloads the group's tables (staged twiddles, phases) into
-// LDS at most once per group.  The next item is prefetched into registers
-// whatever its group.
+// contiguous, so it reloads the group's tables (staged twiddles, the halves
+// k <= N/2 of the two phase rows, the phase being even in k) into LDS at most
+// once per group.  It does not prefetch the next item: on the uneven batch
+// (1D 4096 x 128, 256^2 x 32, 512^2 x 16, 1024^2 x 4) the launch took 178 us
+// with a prefetch register set and 160 us without one, both at two
+// wavefronts per SIMD.
 // --------------------------------------------------------------------------
 template <typename Real>
 struct GroupedX {
   static constexpr int R = 8, THREADS = 256;
   static constexpr int NMAX = sizeof(Real) == 4 ? 1024 : 512;
   static constexpr int ROWS_LDS = (THREADS * R / 16) * 17;  // P (N + N/16) for every N >= 16
-  // FP32: two workgroups per CU, as the single-group kernel gets
+  static constexpr int PH_HALF = NMAX / 2 + 1;                // entries of one half phase row
+  // FP32: two wavefronts per SIMD (at three the kernel spills, and measured slower)
   static constexpr int WAVES_PER_EU = sizeof(Real) == 4 ? 2 : 1;
 };
 
@@ -29,9 +33,11 @@ __device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<
   constexpr int R = 8, T = N / R;
   const int t = tid % T, p = tid / T;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
+  // ph: the half rows k <= N/2 of m = +1 (also m = -1) and m = 0, one after the other
 #pragma unroll
   for (int m = 0; m < 3; ++m)
-    fft_phase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N : 0));
+    fft_halfphase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N / 2 + 1 : 0),
+                                   static_cast<const TabEntry<Real>*>(nullptr));
 }
 
 template <typename Real>
@@ -42,7 +48,7 @@ k_xpass_grouped(XGroupArgs a) {
   constexpr int R = G::R, NMAX = G::NMAX;
   __shared__ C lds[G::ROWS_LDS];
   __shared__ TabEntry<Real> stw[NMAX - R];
-  __shared__ TabEntry<Real> ph[2 * NMAX];
+  __shared__ TabEntry<Real> ph[2 * G::PH_HALF];
   const int tid = threadIdx.x;
   auto group_of = [&](int64_t item) {
     int g = 0;
@@ -64,7 +70,13 @@ k_xpass_grouped(XGroupArgs a) {
   auto load3 = [&](C (&dst)[3][R], int g, int64_t item) {
     int64_t pid;
     int t;
-    if (!place(g, item, &pid, &t)) return;
+    if (!place(g, item, &pid, &t)) {  // a pencil past the group's end: defined values, never stored
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int e = 0; e < R; ++e) dst[m][e] = C{Real(0), Real(0)};
+      return;
+    }
     const int T = a.g[g].n / R;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -76,8 +88,6 @@ k_xpass_grouped(XGroupArgs a) {
   int64_t item = blockIdx.x;
   if (item >= a.item_end) return;
   int cur = -1;
-  C nxt[3][R];
-  load3(nxt, group_of(item), item);
   const Real c0 = Real(a.c0), c1 = Real(a.c1);
   for (; item < a.item_end; item += gridDim.x) {
     const int g = group_of(item);
@@ -98,17 +108,13 @@ k_xpass_grouped(XGroupArgs a) {
             for (int i = tid; i < 1024 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 1024, R>::exponent(i)];
           break;
       }
-      for (int i = tid; i < 2 * n; i += G::THREADS) ph[i] = gph[i];
+      const int h = n / 2 + 1;
+      for (int i = tid; i < 2 * h; i += G::THREADS) ph[i] = gph[i < h ? i : n + (i - h)];
       __syncthreads();
       cur = g;
     }
     C v[3][R];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-      for (int e = 0; e < R; ++e) v[m][e] = nxt[m][e];
-    const int64_t next = item + gridDim.x;
-    if (next < a.item_end) load3(nxt, group_of(next), next);
+    load3(v, g, item);
     int64_t pid;
     int t;
     const bool active = place(g, item, &pid, &t);
