@@ -142,6 +142,18 @@ def test_one_step_2d_all_strided_sizes(lib, ny):
     assert rel(got32, ref) < 2e-6
 
 
+@pytest.mark.parametrize("n", [(16, 1024, 8), (16, 8, 1024), (64, 8, 8)])
+def test_one_step_3d_longest_strided_axes(lib, n):
+    """3D grids with the longest y or z axis (1024 points) and a short one."""
+    grid = (3, n, 0.5, 2)
+    og = O.Grid(3, n, 0.5, 2)
+    psi0 = random_field(n[1] + 7 * n[2], og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(P3), og)
+    for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
+        got = run_gpu(lib, grid, P3, dtype, psi0=psi0, nsteps=1, dt=0.02).fields()[0]
+        assert rel(got, ref) < tol, dtype
+
+
 def test_one_step_3d_non_cubic(lib):
     grid = (3, (32, 16, 8), 0.5, 2)
     og = O.Grid(3, (32, 16, 8), 0.5, 2)
