@@ -377,6 +377,37 @@ def measured_traffic(kernel):
     return float(r["bytes"])
 
 
+VALU_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 FP32 VALU instructions per second (non-packed)
+
+
+def measured_valu(kernel):
+    """VALU wavefront instructions per launch of `kernel` from the committed
+    counter summary, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "valu_xpass_ypass_2d512_s64.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("valu:"):
+            parts = dict(kv.split("=") for kv in line.split()[1:])
+            rec[parts["kind"]] = parts
+    r = rec.get(kernel)
+    if not r or r.get("source") != kernel_source_hash():
+        return None
+    return float(r["instr"])
+
+
+def valu_entry(kernel, avg_ms):
+    """The issue side of the same launch: counted VALU instructions per launch
+    over the live launch time, against the non-packed FP32 issue ceiling."""
+    instr = measured_valu(kernel)
+    if instr is None:
+        return None
+    achieved = instr / (avg_ms / 1e3)
+    return {"instructions_per_launch": instr, "achieved": achieved, "peak": VALU_PEAK, "unit": "wave-instr/s",
+            "frac": achieved / VALU_PEAK}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,7 +498,8 @@ def main():
                    "dt": w["dt"], "params": w["params"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": measured_traffic(dom),
-                     "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes},
+                     "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes,
+                     "valu": valu_entry(dom, dom_avg_ms)},
         "autotuned_variants": variants,
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
         "hbm_algorithmic_GBps_whole_step": None,
