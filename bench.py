@@ -220,6 +220,9 @@ OTHER_CONFIGS = {
     # six times the main batch (2.4 GB of field, beyond the 256 MB last-level cache)
     "2d_512_s384_c64": dict(groups=[(2, (512, 512), 0.5, 384)], dtype="c64", dt=0.02, steps=20,
                             params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002),
+    # the main workload in a harmonic trap V(x) (the V_m of Eq. (4)) rising to 4 at the box faces
+    "2d_512_s64_c64_trap": dict(groups=[(2, (512, 512), 0.5, 64)], dtype="c64", dt=0.02, steps=20,
+                                params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002, trap=4.0),
     "uneven_c64": dict(groups=[(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
                                (2, (1024, 1024), 0.5, 4)], dtype="c64", dt=0.02, steps=100,
                        params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1004),
@@ -238,6 +241,12 @@ def other_configs():
         tuned = sim.autotune(reps=2)
         if c.get("scheme"):
             sim.set_option(spin1.OPT_SCHEME, c["scheme"])
+        if c.get("trap"):
+            import numpy as np
+            g = c["groups"][0]
+            axes = [(np.arange(n) - 0.5 * n) / (0.5 * n) for n in reversed(g[1])]
+            mesh = np.meshgrid(*axes, indexing="ij")
+            sim.set_potential(0, c["trap"] * sum(m ** 2 for m in mesh))
         sim.step(c["steps"], c["dt"])  # capture and warm up
         sim.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -251,6 +260,8 @@ def other_configs():
         out[name] = {"value": sites * c["steps"] / (ms / 1e3), "unit": "site-steps/s", "steps": c["steps"],
                      "ms_per_split_step": ms / c["steps"], "dtype": c["dtype"], "variants": tuned,
                      "norm_sample0": float(obs[0, 0])}
+        if name == MAIN_2D_NAME:
+            out[name]["spin_texture"] = spin_texture_timing(sim)
         if c.get("log"):
             # the same steps with the per-step FP64 (N, F_z, E) log of group 0
             e0.record(sim.stream)
@@ -268,6 +279,31 @@ def other_configs():
         del sim
         torch.cuda.empty_cache()
     return out
+
+
+MAIN_2D_NAME = "2d_512_s384_c64"
+
+
+def spin_texture_timing(sim):
+    """Real-space diagnostics of Fig. 1 on a bound group: spin1_spin_texture
+    (F_perp, per-row FP64 sums, winding) timed over 10 calls; it reads 24 B
+    per site."""
+    import torch
+    from paper_2310_03636_amd import spin1
+
+    g = sim.grids[0]
+    sites = g.samples * g.n[0] * max(g.n[1], 1) * max(g.n[2], 1)
+    with torch.cuda.stream(sim.stream):
+        out = torch.empty((g.samples, 3), dtype=torch.float64, device=sim.device)
+    spin1.spin_texture(sim.ctx, 0, out.data_ptr())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(10):
+        spin1.spin_texture(sim.ctx, 0, out.data_ptr())
+    e1.record(sim.stream)
+    sim.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    return {"ms": ms, "GBps_read": sites * 24 / (ms / 1e3) / 1e9}
 
 
 def full_run():
