@@ -245,14 +245,16 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   First order in dt; it converges to the same flow as dt -> 0.  Reverse
  *   mode and spin1_step_observed take the Strang scheme only
  *   (SPIN1_EUNSUPPORTED otherwise).
- * SPIN1_OPT_FP32_TWIDDLES (complex64 only): SPIN1_TWIDDLES_COMPENSATED
- *   (default) multiplies by the FFT stage twiddles as hi+lo float pairs, so
- *   the constants carry no rounding of their own; SPIN1_TWIDDLES_PLAIN rounds
- *   each twiddle once to a float pair, which halves the cost of those
- *   multiplies but adds a rounding that repeats identically in every step and
- *   so accumulates linearly (the phase tables and the radix constants stay
- *   compensated either way).  Applies to the streaming step passes of
- *   spin1_step; the other passes keep compensated twiddles.
+ * SPIN1_OPT_FP32_TWIDDLES (complex64 only): how the streaming step passes
+ *   of spin1_step hold their FFT stage twiddles and kinetic phase factors.
+ *   SPIN1_TWIDDLES_DITHERED (default): one float pair per value, rebuilt at
+ *   every step as one of the two float pairs next to the FP64 value, chosen
+ *   by error diffusion over the step index within the call so that the mean
+ *   over steps tracks the FP64 value; a multiply costs half the compensated
+ *   one, and the rounding of the constants does not add up step after step.
+ *   SPIN1_TWIDDLES_COMPENSATED: hi+lo float pairs, so the constants carry no
+ *   rounding of their own.  The radix constants and the other passes stay
+ *   compensated either way.
  * SPIN1_OPT_CONCURRENT_GROUPS: 1 (default) = when a grouped x-pass runs,
  *   spin1_step issues the steps of the remaining groups on a second stream
  *   of the library's (default priority, created on first use), forked from
@@ -275,7 +277,7 @@ enum spin1_option {
   SPIN1_OPT_1D_KERNEL = 7
 };
 enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
-enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_PLAIN = 1 };
+enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_DITHERED = 1 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);
 
 /* Kernel kinds reported by the profiling hooks. */

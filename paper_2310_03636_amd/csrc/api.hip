@@ -219,7 +219,7 @@ struct spin1_ctx {
   bool grouped_x = true;
   int kernel_1d = 0;  // 0 automatic, 1 one thread group per sample, 2 component groups
   int scheme = SPIN1_SCHEME_STRANG;
-  bool plain_twiddles = false;
+  bool dithered_tables = true;  // FP32 streaming passes: dithered float tables
   // groups outside the grouped x-pass run on a second stream of default
   // priority, forked from and joined back into the caller's stream per call
   bool concurrent = true;
@@ -371,7 +371,7 @@ int log2_of(int n) {
   return r;
 }
 
-int twiddle_offset(const spin1_ctx* ctx) { return ctx->plain_twiddles && !ctx->dbl ? kPlainTwiddles : 0; }
+int twiddle_offset(const spin1_ctx* ctx) { return ctx->dithered_tables && !ctx->dbl ? kPlainTwiddles : 0; }
 
 int variant_of(spin1_ctx* ctx, int pass, int n) {
   return ctx->variant[pass][ctx->dbl ? 1 : 0][log2_of(n)] + twiddle_offset(ctx);
@@ -390,6 +390,7 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
   for (int a = 1; a < G.geo.dim; ++a) {
     SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
     sa.reverse = pass_reverse(step * G.geo.dim + a);
+    sa.tick = step;
     {
       Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
       e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa, variant_of(ctx, 1, G.geo.n[a]));
@@ -414,6 +415,7 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
   xa.psi = field;
   xa.src = src;
   xa.reverse = pass_reverse(step * G.geo.dim);
+  xa.tick = step;
   xa.tau_pre = tau_open;
   xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
   hipError_t e;
@@ -1254,9 +1256,9 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_FP32_TWIDDLES:
-      if (value != SPIN1_TWIDDLES_COMPENSATED && value != SPIN1_TWIDDLES_PLAIN)
+      if (value != SPIN1_TWIDDLES_COMPENSATED && value != SPIN1_TWIDDLES_DITHERED)
         return fail(SPIN1_EINVAL, "unknown twiddle precision");
-      ctx->plain_twiddles = value == SPIN1_TWIDDLES_PLAIN;
+      ctx->dithered_tables = value == SPIN1_TWIDDLES_DITHERED;
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_GROUPED_X:

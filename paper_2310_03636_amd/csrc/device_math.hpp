@@ -68,6 +68,21 @@ __device__ __forceinline__ Cx<double> mul_tab(Cx<double> x, TabEntry<double> w) 
   return {x.re * w.hr - x.im * w.hi, x.re * w.hi + x.im * w.hr};
 }
 
+// One of the two floats next to the FP64 value h + l (h = nearest float, l the
+// remainder), chosen per tick so that the running mean of the choices over
+// consecutive ticks tracks h + l (error diffusion with a per-entry offset
+// `salt`): the rounding of a constant used once per step then does not add up
+// step after step.
+__device__ __forceinline__ float dither_round(float h, float l, int64_t tick, uint32_t salt) {
+  if (l == 0.0f) return h;
+  const float alt = nextafterf(h, l > 0.0f ? __builtin_inff() : -__builtin_inff());
+  const double p = double(l) / double(alt - h);  // in (0, 1/2]
+  const double off = double(salt) * (1.0 / 4294967296.0);
+  const bool up = floor(p * double(tick + 1) + off) > floor(p * double(tick) + off);
+  return up ? alt : h;
+}
+__device__ __forceinline__ uint32_t dither_salt(uint32_t i) { return i * 2654435761u; }
+
 // multiply by a table value kept as one plain complex number (rounded once)
 template <typename Real>
 __device__ __forceinline__ Cx<Real> mul_tab(Cx<Real> x, Cx<Real> w) {
@@ -281,10 +296,11 @@ __device__ __forceinline__ void fft_pencil(Cx<Real>* v, int t, Lds& lds, const T
 }
 
 // Forward FFT, multiply by ph[k] (which carries the 1/N of the inverse),
-// inverse FFT through conj(FFT(conj(.))).  ph is in natural k order.
-template <typename Real, int N, int R, class Lds, class TW>
+// inverse FFT through conj(FFT(conj(.))).  ph is in natural k order; its
+// entries are TabEntry (hi + lo) or plain complex values (PE).
+template <typename Real, int N, int R, class Lds, class TW, class PE>
 __device__ __forceinline__ void fft_phase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
-                                               const TabEntry<Real>* __restrict__ ph) {
+                                               const PE* __restrict__ ph) {
   constexpr int T = N / R;
   fft_pencil<Real, N, R>(v, t, lds, tw);
 #pragma unroll
@@ -312,10 +328,9 @@ struct HalfTwiddles {
 // in k) and, when zq is given, by the uniform factor *zq, inverse FFT.
 // Element e of thread t is k = t + e*N/R: below N/2 for e < R/2, at or above
 // it otherwise, so the mirror choice is static.
-template <typename Real, int N, int R, class Lds, class TW>
+template <typename Real, int N, int R, class Lds, class TW, class PE>
 __device__ __forceinline__ void fft_halfphase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
-                                                   const TabEntry<Real>* __restrict__ ph0,
-                                                   const TabEntry<Real>* zq) {
+                                                   const PE* __restrict__ ph0, const PE* zq) {
   constexpr int T = N / R;
   static_assert(R >= 2, "the static mirror split needs two halves");
   fft_pencil<Real, N, R>(v, t, lds, tw);

@@ -44,6 +44,7 @@ struct XPassArgs {
   double power_scale;  // SF_POWER: 1 / N_sites
   int lg_rows;      // log2(rows), set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
+  int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
 };
 
 // One x-pass launch over the step passes of several groups (pencil lengths
@@ -82,6 +83,7 @@ struct SPassArgs {
   double power_scale;
   int lg_tiles, lg_outer;  // log2 of (inner / TX) and of outer, set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
+  int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
 };
 
 hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,
@@ -89,7 +91,7 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
 hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
                        double n0, double wigner_var);
 // variant: step-pass variant index (0 = default), ignored by the other modes
-// step-pass variant offset selecting plain (once-rounded) FP32 stage twiddles
+// step-pass variant offset selecting the dithered plain FP32 tables (twiddles and phases)
 constexpr int kPlainTwiddles = 3;
 hipError_t launch_xpass(hipStream_t st, bool dbl, int mode, int n, const XPassArgs& a, int variant = 0);
 hipError_t launch_spass(hipStream_t st, bool dbl, int mode, int n, const SPassArgs& a, int variant = 0);

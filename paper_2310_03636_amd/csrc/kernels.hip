@@ -183,7 +183,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
 // --------------------------------------------------------------------------
 // launchers
 // --------------------------------------------------------------------------
-// variant: 0..2 the step-pass variant; + kPlainTwiddles for plain FP32 twiddles
+// variant: 0..2 the step-pass variant; + kPlainTwiddles for the dithered plain FP32 tables
 template <typename Real, int N, int MODE>
 static hipError_t xpass_n(hipStream_t st, const XPassArgs& a, int variant) {
   if constexpr (MODE == MODE_STEP && XCfg<N, Real>::STREAM) {

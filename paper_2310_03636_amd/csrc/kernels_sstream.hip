@@ -20,6 +20,7 @@ namespace spin1 {
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
 // prefetch had arrived (the vector-memory counter retires in order).
+// PLAIN: plain complex twiddles and phase factors, dithered per step (FP32).
 template <typename Real, int N, int V, bool PLAIN>
 __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
@@ -27,7 +28,8 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
   __shared__ C lds[N * ColLds<Real, TX>::PITCH];
   using TE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
   __shared__ TE tw[N];
-  __shared__ TabEntry<Real> ph[N / 2 + 1];  // the phase is even in k
+  using PE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
+  __shared__ PE ph[N / 2 + 1];  // the phase is even in k
   const int c = threadIdx.x % TX;
   const int t = threadIdx.x / TX;
   const int64_t tiles = a.inner / TX;
@@ -37,11 +39,18 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
       if constexpr (PLAIN)
-        tw[i] = C{gtw[i].hr, gtw[i].hi};
+        tw[i] = C{dither_round(gtw[i].hr, gtw[i].lr, a.tick, dither_salt(2 * i)),
+                  dither_round(gtw[i].hi, gtw[i].li, a.tick, dither_salt(2 * i + 1))};
       else
         tw[i] = gtw[i];
     }
-    for (int i = threadIdx.x; i <= N / 2; i += blockDim.x) ph[i] = gph[i];
+    for (int i = threadIdx.x; i <= N / 2; i += blockDim.x) {
+      if constexpr (PLAIN)
+        ph[i] = C{dither_round(gph[i].hr, gph[i].lr, a.tick, dither_salt(2 * (i + N))),
+                  dither_round(gph[i].hi, gph[i].li, a.tick, dither_salt(2 * (i + N) + 1))};
+      else
+        ph[i] = gph[i];
+    }
     __syncthreads();
   }
   // item -> (field f, outer o, tile): shifts, all three extents are powers of two
@@ -74,8 +83,8 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
 #pragma unroll
       for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
     }
-    fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), ph,
-                                   static_cast<const TabEntry<Real>*>(nullptr));
+    fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), static_cast<const PE*>(ph),
+                                   static_cast<const PE*>(nullptr));
 #pragma unroll
     for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
   }

@@ -20,9 +20,10 @@ namespace spin1 {
 // The twiddle and phase tables are staged in LDS once per workgroup: a global
 // load issued after the prefetch could only be consumed once the whole
 // prefetch had arrived (the vector-memory counter retires in order).
-// PLAIN: the stage twiddles rounded once to plain complex values (FP32 only):
-// half the multiply cost and LDS of the hi+lo form, at a larger systematic
-// rounding of the transform (see the precision option in spin1.h)
+// PLAIN: the stage twiddles and phase factors held as plain complex values
+// (FP32 only), rebuilt per launch as the dithered rounding of the FP64 value
+// for the step index `tick` (dither_round): half the multiply cost and LDS of
+// the hi+lo form, and no rounding that repeats identically in every step
 // POT: the group has a trap potential (a separate instantiation, so that the
 // common case keeps its register budget)
 template <typename Real, int N, int V, bool PLAIN, bool POT = false, bool ENABLED = XCfg<N, Real, V>::STREAM>
@@ -36,7 +37,8 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
   using TWA = std::conditional_t<PLAIN, StagedTwiddlesPlain<Real, N, R>, TW>;
   __shared__ TE stw[TW::SIZE > 0 ? TW::SIZE : 1];
   // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
-  __shared__ TabEntry<Real> ph[2 * N];
+  using PE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
+  __shared__ PE ph[2 * N];
   const int t = threadIdx.x % T;
   const int p = threadIdx.x / T;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
@@ -46,11 +48,18 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XP
     for (int i = threadIdx.x; i < TW::SIZE; i += blockDim.x) {
       const TabEntry<Real> w = gtw[TW::exponent(i)];
       if constexpr (PLAIN)
-        stw[i] = C{w.hr, w.hi};
+        stw[i] = C{dither_round(w.hr, w.lr, a.tick, dither_salt(2 * i)),
+                   dither_round(w.hi, w.li, a.tick, dither_salt(2 * i + 1))};
       else
         stw[i] = w;
     }
-    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) ph[i] = gph[i];
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+      if constexpr (PLAIN)
+        ph[i] = C{dither_round(gph[i].hr, gph[i].lr, a.tick, dither_salt(2 * (i + N))),
+                  dither_round(gph[i].hi, gph[i].li, a.tick, dither_salt(2 * (i + N) + 1))};
+      else
+        ph[i] = gph[i];
+    }
     __syncthreads();
   }
   C* psi = static_cast<C*>(a.psi);
