@@ -76,9 +76,11 @@ __device__ __forceinline__ Cx<double> mul_tab(Cx<double> x, TabEntry<double> w) 
 __device__ __forceinline__ float dither_round(float h, float l, int64_t tick, uint32_t salt) {
   if (l == 0.0f) return h;
   const float alt = nextafterf(h, l > 0.0f ? __builtin_inff() : -__builtin_inff());
-  const double p = double(l) / double(alt - h);  // in (0, 1/2]
-  const double off = double(salt) * (1.0 / 4294967296.0);
-  const bool up = floor(p * double(tick + 1) + off) > floor(p * double(tick) + off);
+  const float p = l / (alt - h);  // in (0, 1/2]
+  // the pattern repeats every 2^16 steps; within that, float holds p * tick
+  // to well under one unit
+  const float k = float(tick & 0xffff), off = float(salt >> 8) * (1.0f / 16777216.0f);
+  const bool up = floorf(fmaf(p, k + 1.0f, off)) > floorf(fmaf(p, k, off));
   return up ? alt : h;
 }
 __device__ __forceinline__ uint32_t dither_salt(uint32_t i) { return i * 2654435761u; }

@@ -27,7 +27,9 @@ namespace spin1 {
 // POT: the group has a trap potential (a separate instantiation, so that the
 // common case keeps its register budget)
 template <typename Real, int N, int V, bool PLAIN, bool POT = false, bool ENABLED = XCfg<N, Real, V>::STREAM>
-__global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) void k_xpass_stream(XPassArgs a, int64_t groups) {
+__global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
+    amdgpu_waves_per_eu((PLAIN && !POT && sizeof(Real) == 4 && N <= 512) ? 3 : 1))) void k_xpass_stream(XPassArgs a,
+                                                                                                       int64_t groups) {
  if constexpr (ENABLED) {
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real, V>::R, T = XCfg<N, Real, V>::T, P = XCfg<N, Real, V>::P;
