@@ -246,7 +246,8 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   mode and spin1_step_observed take the Strang scheme only
  *   (SPIN1_EUNSUPPORTED otherwise).
  * SPIN1_OPT_FP32_TWIDDLES (complex64 only): how the streaming step passes
- *   of spin1_step hold their FFT stage twiddles and kinetic phase factors.
+ *   of spin1_step (and the grouped x-pass) hold their FFT stage twiddles and
+ *   kinetic phase factors.
  *   SPIN1_TWIDDLES_DITHERED (default): one float pair per value, rebuilt at
  *   every step as one of the two float pairs next to the FP64 value, chosen
  *   by error diffusion over the step index within the call so that the mean

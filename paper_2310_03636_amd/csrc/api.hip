@@ -498,7 +498,8 @@ std::vector<size_t> grouped_x_set(const spin1_ctx* ctx) {
   return out;
 }
 
-int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau_open, double tau_close) {
+int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau_open, double tau_close,
+                      int64_t step) {
   XGroupArgs ga{};
   int64_t items = 0;
   for (size_t j = 0; j < set.size(); ++j) {
@@ -521,6 +522,9 @@ int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau
   ga.tau_pre = tau_open;
   ga.c0 = ctx->p.c0;
   ga.c1 = ctx->p.c1;
+  ga.dither = twiddle_offset(ctx) != 0;
+  ga.tick = step;
+  dithered_radix(step, ga.rc);
   hipError_t e;
   {
     Prof pr(ctx, SPIN1_K_XPASS);
@@ -630,7 +634,7 @@ int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
   for (int64_t i = 0; i < n && !set.empty(); ++i) {
     const double pre = i == 0 ? 0.5 * dt : dt;
     const double close = i == n - 1 ? 0.5 * dt : 0.0;
-    rc = enqueue_grouped_x(ctx, set, pre, close);
+    rc = enqueue_grouped_x(ctx, set, pre, close, i);
     for (size_t g : set)
       if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close, i);
     if (rc) break;

@@ -66,6 +66,9 @@ struct XGroupArgs {
   int64_t item_end;  // item_begin of a virtual group past the last
   int ngroups;
   double tau_pre, c0, c1;
+  int dither;        // FP32: dithered plain tables and radix constants for step `tick`
+  int64_t tick;
+  float rc[9];       // dithered cos(pi k / 16), k = 0..8
 };
 
 struct SPassArgs {

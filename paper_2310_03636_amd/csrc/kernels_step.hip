@@ -27,28 +27,48 @@ struct GroupedX {
   static constexpr int WAVES_PER_EU = sizeof(Real) == 4 ? 2 : 1;
 };
 
-template <typename Real, int N>
-__device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<Real>* lds,
-                                               const TabEntry<Real>* stw, const TabEntry<Real>* ph) {
+// DITHER: plain complex tables (dithered per step) and the step's radix set
+template <typename Real, int N, bool DITHER, class TE>
+__device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<Real>* lds, const TE* stw,
+                                               const TE* ph, const RadixSet& rs) {
   constexpr int R = 8, T = N / R;
   const int t = tid % T, p = tid / T;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
   // ph: the half rows k <= N/2 of m = +1 (also m = -1) and m = 0, one after the other
 #pragma unroll
-  for (int m = 0; m < 3; ++m)
-    fft_halfphase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N / 2 + 1 : 0),
-                                   static_cast<const TabEntry<Real>*>(nullptr));
+  for (int m = 0; m < 3; ++m) {
+    if constexpr (DITHER)
+      fft_halfphase_ifft<Real, N, R>(v[m], t, L, WithRadix<StagedTwiddlesPlain<Real, N, R>>{{stw}, rs},
+                                     ph + (m == 1 ? N / 2 + 1 : 0), static_cast<const TE*>(nullptr));
+    else
+      fft_halfphase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N / 2 + 1 : 0),
+                                     static_cast<const TE*>(nullptr));
+  }
 }
 
-template <typename Real>
+template <typename Real, bool DITHER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GroupedX<Real>::WAVES_PER_EU))) void
 k_xpass_grouped(XGroupArgs a) {
   using C = Cx<Real>;
   using G = GroupedX<Real>;
+  using TE = std::conditional_t<DITHER, C, TabEntry<Real>>;
   constexpr int R = G::R, NMAX = G::NMAX;
   __shared__ C lds[G::ROWS_LDS];
-  __shared__ TabEntry<Real> stw[NMAX - R];
-  __shared__ TabEntry<Real> ph[2 * G::PH_HALF];
+  __shared__ TE stw[NMAX - R];
+  __shared__ TE ph[2 * G::PH_HALF];
+  RadixSet rs{};
+  if constexpr (DITHER) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rs.d[k] = a.rc[k];
+  }
+  // a table entry in the kernel's form: hi+lo, or the dithered float pair
+  auto entry = [&](const TabEntry<Real>& w, uint32_t i) -> TE {
+    if constexpr (DITHER)
+      return C{dither_round(w.hr, w.lr, a.tick, dither_salt(2 * i)),
+               dither_round(w.hi, w.li, a.tick, dither_salt(2 * i + 1))};
+    else
+      return w;
+  };
   const int tid = threadIdx.x;
   auto group_of = [&](int64_t item) {
     int g = 0;
@@ -97,19 +117,20 @@ k_xpass_grouped(XGroupArgs a) {
       const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.g[g].tw);
       const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.g[g].ph);
       switch (n) {
-        case 16: for (int i = tid; i < 16 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 16, R>::exponent(i)]; break;
-        case 32: for (int i = tid; i < 32 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 32, R>::exponent(i)]; break;
-        case 64: for (int i = tid; i < 64 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 64, R>::exponent(i)]; break;
-        case 128: for (int i = tid; i < 128 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 128, R>::exponent(i)]; break;
-        case 256: for (int i = tid; i < 256 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 256, R>::exponent(i)]; break;
-        case 512: for (int i = tid; i < 512 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 512, R>::exponent(i)]; break;
+        case 16: for (int i = tid; i < 16 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 16, R>::exponent(i)], i); break;
+        case 32: for (int i = tid; i < 32 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 32, R>::exponent(i)], i); break;
+        case 64: for (int i = tid; i < 64 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 64, R>::exponent(i)], i); break;
+        case 128: for (int i = tid; i < 128 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 128, R>::exponent(i)], i); break;
+        case 256: for (int i = tid; i < 256 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 256, R>::exponent(i)], i); break;
+        case 512: for (int i = tid; i < 512 - R; i += G::THREADS) stw[i] = entry(gtw[StagedTwiddles<Real, 512, R>::exponent(i)], i); break;
         default:
           if constexpr (NMAX >= 1024)
-            for (int i = tid; i < 1024 - R; i += G::THREADS) stw[i] = gtw[StagedTwiddles<Real, 1024, R>::exponent(i)];
+            for (int i = tid; i < 1024 - R; i += G::THREADS)
+              stw[i] = entry(gtw[StagedTwiddles<Real, 1024, R>::exponent(i)], i);
           break;
       }
       const int h = n / 2 + 1;
-      for (int i = tid; i < 2 * h; i += G::THREADS) ph[i] = gph[i < h ? i : n + (i - h)];
+      for (int i = tid; i < 2 * h; i += G::THREADS) ph[i] = entry(gph[i < h ? i : n + (i - h)], i + 4096);
       __syncthreads();
       cur = g;
     }
@@ -130,14 +151,14 @@ k_xpass_grouped(XGroupArgs a) {
       }
     }
     switch (a.g[g].n) {
-      case 16: grouped_x_body<Real, 16>(v, tid, lds, stw, ph); break;
-      case 32: grouped_x_body<Real, 32>(v, tid, lds, stw, ph); break;
-      case 64: grouped_x_body<Real, 64>(v, tid, lds, stw, ph); break;
-      case 128: grouped_x_body<Real, 128>(v, tid, lds, stw, ph); break;
-      case 256: grouped_x_body<Real, 256>(v, tid, lds, stw, ph); break;
-      case 512: grouped_x_body<Real, 512>(v, tid, lds, stw, ph); break;
+      case 16: grouped_x_body<Real, 16, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 32: grouped_x_body<Real, 32, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 64: grouped_x_body<Real, 64, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 128: grouped_x_body<Real, 128, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 256: grouped_x_body<Real, 256, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 512: grouped_x_body<Real, 512, DITHER>(v, tid, lds, stw, ph, rs); break;
       default:
-        if constexpr (NMAX >= 1024) grouped_x_body<Real, 1024>(v, tid, lds, stw, ph);
+        if constexpr (NMAX >= 1024) grouped_x_body<Real, 1024, DITHER>(v, tid, lds, stw, ph, rs);
         break;
     }
     if (a.g[g].tau_post != 0.0) {
@@ -353,8 +374,15 @@ static hipError_t xpass_grouped_t(hipStream_t st, const XGroupArgs& a) {
     if ((e.rows & (e.rows - 1)) != 0 || (int64_t(1) << e.lg_rows) != e.rows) return hipErrorInvalidValue;
   }
   if (a.g[0].item_begin != 0 || a.item_end < 1) return hipErrorInvalidValue;
-  const int64_t grid = stream_grid(k_xpass_grouped<Real>, GroupedX<Real>::THREADS, a.item_end);
-  hipLaunchKernelGGL(k_xpass_grouped<Real>, dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
+  if constexpr (sizeof(Real) == 4) {
+    if (a.dither) {
+      const int64_t grid = stream_grid(k_xpass_grouped<Real, true>, GroupedX<Real>::THREADS, a.item_end);
+      hipLaunchKernelGGL((k_xpass_grouped<Real, true>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  const int64_t grid = stream_grid(k_xpass_grouped<Real, false>, GroupedX<Real>::THREADS, a.item_end);
+  hipLaunchKernelGGL((k_xpass_grouped<Real, false>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
