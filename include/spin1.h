@@ -253,10 +253,9 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   by error diffusion over the step index within the call so that the mean
  *   over steps tracks the FP64 value; a multiply costs half the compensated
  *   one, and the rounding of the constants does not add up step after step.
- *   The irrational radix constants of the in-register butterflies are
- *   dithered the same way.  SPIN1_TWIDDLES_COMPENSATED: hi+lo float pairs for
- *   tables and radix constants, so the constants carry no rounding of their
- *   own.  The other passes use the compensated form either way.
+ *   SPIN1_TWIDDLES_COMPENSATED: hi+lo float pairs, so the constants carry no
+ *   rounding of their own.  The radix constants of the in-register
+ *   butterflies and the other passes use the compensated form either way.
  * SPIN1_OPT_CONCURRENT_GROUPS: 1 (default) = when a grouped x-pass runs,
  *   spin1_step issues the steps of the remaining groups on a second stream
  *   of the library's (default priority, created on first use), forked from

@@ -331,27 +331,6 @@ int upload_shells(spin1_ctx* ctx, GroupState& G) {
   return SPIN1_OK;
 }
 
-// The radix constants cos(pi k / 16), k = 0..8, for step `tick` in the dithered
-// FP32 form: each irrational one is the lower or upper float next to its FP64
-// value, chosen by error diffusion over the ticks (with a per-constant offset)
-// so that the mean over the steps of a call tracks the FP64 value.
-void dithered_radix(int64_t tick, float* d) {
-  for (int k = 0; k <= 8; ++k) {
-    const double v = std::cos(M_PI * k / 16.0);
-    const float h = float(v);
-    const double l = v - double(h);
-    d[k] = h;
-    if (l == 0.0) continue;
-    const float alt = std::nextafter(h, l > 0 ? INFINITY : -INFINITY);
-    const double p = l / (double(alt) - double(h));
-    const double off = double((uint32_t(k + 4096) * 2654435761u) >> 8) / 16777216.0;
-    const double t = double(tick & 0xffff);
-    if (std::floor(p * (t + 1.0) + off) > std::floor(p * t + off)) d[k] = alt;
-  }
-  d[0] = 1.0f;
-  d[8] = 0.0f;
-}
-
 XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
   XPassArgs a{};
   a.psi = G.psi;
@@ -366,7 +345,6 @@ XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
   a.q = ctx->p.q;
   a.kscale = 2.0 * M_PI / (double(G.geo.n[0]) * G.geo.dx);
   a.power_scale = 1.0 / double(G.geo.sites);
-  dithered_radix(0, a.rc);
   return a;
 }
 
@@ -375,7 +353,6 @@ SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int6
   a.psi = field;
   a.tw = at(ctx, G.lay.tw[axis]);
   a.ph = at(ctx, G.lay.ph[axis]);
-  dithered_radix(0, a.rc);
   spass_geom(G.geo, axis, &a.sa, &a.inner, &a.outer, &a.outer_stride);
   a.nfield = nfield;
   a.field_stride = G.geo.sites;
@@ -415,7 +392,6 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
     SPassArgs sa = sargs(ctx, G, a, field, int64_t(3) * G.geo.S);
     sa.reverse = pass_reverse(step * G.geo.dim + a);
     sa.tick = step;
-    dithered_radix(step, sa.rc);
     {
       Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
       e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa, variant_of(ctx, 1, G.geo.n[a]));
@@ -441,7 +417,6 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
   xa.src = src;
   xa.reverse = pass_reverse(step * G.geo.dim);
   xa.tick = step;
-  dithered_radix(step, xa.rc);
   xa.tau_pre = tau_open;
   xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
   hipError_t e;
@@ -524,7 +499,6 @@ int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau
   ga.c1 = ctx->p.c1;
   ga.dither = twiddle_offset(ctx) != 0;
   ga.tick = step;
-  dithered_radix(step, ga.rc);
   hipError_t e;
   {
     Prof pr(ctx, SPIN1_K_XPASS);

@@ -136,18 +136,8 @@ constexpr double sin_pi16(int i) { return i <= 8 ? kCos32[8 - i] : kCos32[i - 8]
 // v * exp(-2 pi i K / R) = v * exp(-i pi I / 16), I = K * 32 / R < 16; the
 // irrational constants go through mul_const / dot_const so the single-
 // precision path uses them at full FP64 accuracy
-// Source of the radix constants: CompensatedRadix (the FP64 values above,
-// hi+lo in FP32) or, for kernels that pass one, a RadixSet of plain floats
-// d[k] ~ cos(pi k / 16), k = 0..8, dithered per step like the tables.
-struct CompensatedRadix {};
-struct RadixSet {
-  float d[9];
-};
-template <class RC>
-inline constexpr bool kDitheredRadix = std::is_same_v<RC, RadixSet>;
-
-template <typename Real, int R, int K, class RC>
-__device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v, const RC& rc) {
+template <typename Real, int R, int K>
+__device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v) {
   static_assert(R <= 32 && 2 * K < R, "twiddle of a radix <= 32 half");
   constexpr int I = K * (32 / R);
   constexpr double h = 0.70710678118654752440;
@@ -155,11 +145,6 @@ __device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v, const RC& rc) {
     return v;
   } else if constexpr (I == 8) {
     return {v.im, -v.re};
-  } else if constexpr (kDitheredRadix<RC>) {
-    // cos(pi I/16) and sin(pi I/16) from the dithered table (sign by symmetry)
-    const float c = I <= 8 ? rc.d[I] : -rc.d[16 - I];
-    const float sn = I <= 8 ? rc.d[8 - I] : rc.d[I - 8];
-    return {fmaf(v.re, c, v.im * sn), fmaf(v.im, c, -(v.re * sn))};
   } else if constexpr (I == 4) {
     return {mul_const<Real>(v.re + v.im, h), mul_const<Real>(v.im - v.re, h)};
   } else if constexpr (I == 12) {
@@ -171,18 +156,18 @@ __device__ __forceinline__ Cx<Real> twiddle_const(Cx<Real> v, const RC& rc) {
   }
 }
 
-template <typename Real, int R, int K, class RC>
-__device__ __forceinline__ void dft_combine(Cx<Real>* v, const Cx<Real>* e, const Cx<Real>* o, const RC& rc) {
+template <typename Real, int R, int K>
+__device__ __forceinline__ void dft_combine(Cx<Real>* v, const Cx<Real>* e, const Cx<Real>* o) {
   if constexpr (K < R / 2) {
-    const Cx<Real> t = twiddle_const<Real, R, K>(o[K], rc);
+    const Cx<Real> t = twiddle_const<Real, R, K>(o[K]);
     v[K] = e[K] + t;
     v[K + R / 2] = e[K] - t;
-    dft_combine<Real, R, K + 1>(v, e, o, rc);
+    dft_combine<Real, R, K + 1>(v, e, o);
   }
 }
 
-template <typename Real, int R, class RC = CompensatedRadix>
-__device__ __forceinline__ void dft(Cx<Real>* v, const RC& rc = RC{}) {
+template <typename Real, int R>
+__device__ __forceinline__ void dft(Cx<Real>* v) {
   static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16 || R == 32, "radix");
   if constexpr (R == 2) {
     const Cx<Real> a = v[0], b = v[1];
@@ -195,9 +180,9 @@ __device__ __forceinline__ void dft(Cx<Real>* v, const RC& rc = RC{}) {
       e[i] = v[2 * i];
       o[i] = v[2 * i + 1];
     }
-    dft<Real, R / 2>(e, rc);
-    dft<Real, R / 2>(o, rc);
-    dft_combine<Real, R, 0>(v, e, o, rc);
+    dft<Real, R / 2>(e);
+    dft<Real, R / 2>(o);
+    dft_combine<Real, R, 0>(v, e, o);
   }
 }
 
@@ -266,23 +251,6 @@ __device__ __forceinline__ Cx<Real> tw_at(const StagedTwiddlesPlain<Real, N, R>&
   return tw.t[(Ns - R) + (r - 1) * Ns + j];
 }
 
-// A twiddle table together with the dithered radix constants of the same
-// step: tw_at forwards to the table, fft_stages takes the constants from it.
-template <class TW>
-struct WithRadix {
-  TW tw;
-  RadixSet rc;
-  __device__ __forceinline__ auto operator[](int m) const { return tw[m]; }
-};
-template <int N, int Ns, int Rs, class TW>
-__device__ __forceinline__ auto tw_at(const WithRadix<TW>& w, int j, int r) {
-  return tw_at<N, Ns, Rs>(w.tw, j, r);
-}
-template <class TW>
-__device__ __forceinline__ CompensatedRadix radix_of(const TW&) { return {}; }
-template <class TW>
-__device__ __forceinline__ const RadixSet& radix_of(const WithRadix<TW>& w) { return w.rc; }
-
 // TW: see tw_at
 template <typename Real, int N, int R, int Ns, class Lds, class TW>
 __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const TW& tw) {
@@ -303,7 +271,7 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const T
 #pragma unroll
         for (int r = 1; r < Rs; ++r) w[r] = mul_tab(w[r], tw_at<N, Ns, Rs>(tw, j, r));
       }
-      dft<Real, Rs>(w, radix_of(tw));
+      dft<Real, Rs>(w);
       if constexpr (last) {
 #pragma unroll
         for (int r = 0; r < Rs; ++r) v[u + r * U] = w[r];

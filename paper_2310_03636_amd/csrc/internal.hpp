@@ -45,7 +45,6 @@ struct XPassArgs {
   int lg_rows;      // log2(rows), set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
   int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
-  float rc[9];      // STEP, dithered FP32 tables: cos(pi k / 16), k = 0..8, dithered for the step
 };
 
 // One x-pass launch over the step passes of several groups (pencil lengths
@@ -66,9 +65,8 @@ struct XGroupArgs {
   int64_t item_end;  // item_begin of a virtual group past the last
   int ngroups;
   double tau_pre, c0, c1;
-  int dither;        // FP32: dithered plain tables and radix constants for step `tick`
+  int dither;        // FP32: dithered plain tables for step `tick`
   int64_t tick;
-  float rc[9];       // dithered cos(pi k / 16), k = 0..8
 };
 
 struct SPassArgs {
@@ -88,7 +86,6 @@ struct SPassArgs {
   int lg_tiles, lg_outer;  // log2 of (inner / TX) and of outer, set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
   int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
-  float rc[9];      // STEP, dithered FP32 tables: cos(pi k / 16), k = 0..8, dithered for the step
 };
 
 hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,

@@ -53,13 +53,6 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
     }
     __syncthreads();
   }
-  // plain form: the table with the step's dithered radix constants
-  WithRadix<const TE*> twr{};
-  twr.tw = tw;
-  if constexpr (PLAIN) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) twr.rc.d[k] = a.rc[k];
-  }
   // item -> (field f, outer o, tile): shifts, all three extents are powers of two
   char* psi = static_cast<char*>(a.psi);
   const uint32_t lane_off = uint32_t((c + int64_t(t) * a.sa) * int64_t(sizeof(C)));
@@ -90,11 +83,8 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
 #pragma unroll
       for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
     }
-    if constexpr (PLAIN)
-      fft_halfphase_ifft<Real, N, R>(v, t, L, twr, static_cast<const PE*>(ph), static_cast<const PE*>(nullptr));
-    else
-      fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), static_cast<const PE*>(ph),
-                                     static_cast<const PE*>(nullptr));
+    fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), static_cast<const PE*>(ph),
+                                   static_cast<const PE*>(nullptr));
 #pragma unroll
     for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
   }

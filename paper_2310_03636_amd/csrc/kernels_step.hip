@@ -27,10 +27,10 @@ struct GroupedX {
   static constexpr int WAVES_PER_EU = sizeof(Real) == 4 ? 2 : 1;
 };
 
-// DITHER: plain complex tables (dithered per step) and the step's radix set
+// DITHER: plain complex tables, dithered per step
 template <typename Real, int N, bool DITHER, class TE>
 __device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<Real>* lds, const TE* stw,
-                                               const TE* ph, const RadixSet& rs) {
+                                               const TE* ph) {
   constexpr int R = 8, T = N / R;
   const int t = tid % T, p = tid / T;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
@@ -38,8 +38,8 @@ __device__ __forceinline__ void grouped_x_body(Cx<Real> (&v)[3][8], int tid, Cx<
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     if constexpr (DITHER)
-      fft_halfphase_ifft<Real, N, R>(v[m], t, L, WithRadix<StagedTwiddlesPlain<Real, N, R>>{{stw}, rs},
-                                     ph + (m == 1 ? N / 2 + 1 : 0), static_cast<const TE*>(nullptr));
+      fft_halfphase_ifft<Real, N, R>(v[m], t, L, StagedTwiddlesPlain<Real, N, R>{stw}, ph + (m == 1 ? N / 2 + 1 : 0),
+                                     static_cast<const TE*>(nullptr));
     else
       fft_halfphase_ifft<Real, N, R>(v[m], t, L, StagedTwiddles<Real, N, R>{stw}, ph + (m == 1 ? N / 2 + 1 : 0),
                                      static_cast<const TE*>(nullptr));
@@ -56,11 +56,6 @@ k_xpass_grouped(XGroupArgs a) {
   __shared__ C lds[G::ROWS_LDS];
   __shared__ TE stw[NMAX - R];
   __shared__ TE ph[2 * G::PH_HALF];
-  RadixSet rs{};
-  if constexpr (DITHER) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) rs.d[k] = a.rc[k];
-  }
   // a table entry in the kernel's form: hi+lo, or the dithered float pair
   auto entry = [&](const TabEntry<Real>& w, uint32_t i) -> TE {
     if constexpr (DITHER)
@@ -151,14 +146,14 @@ k_xpass_grouped(XGroupArgs a) {
       }
     }
     switch (a.g[g].n) {
-      case 16: grouped_x_body<Real, 16, DITHER>(v, tid, lds, stw, ph, rs); break;
-      case 32: grouped_x_body<Real, 32, DITHER>(v, tid, lds, stw, ph, rs); break;
-      case 64: grouped_x_body<Real, 64, DITHER>(v, tid, lds, stw, ph, rs); break;
-      case 128: grouped_x_body<Real, 128, DITHER>(v, tid, lds, stw, ph, rs); break;
-      case 256: grouped_x_body<Real, 256, DITHER>(v, tid, lds, stw, ph, rs); break;
-      case 512: grouped_x_body<Real, 512, DITHER>(v, tid, lds, stw, ph, rs); break;
+      case 16: grouped_x_body<Real, 16, DITHER>(v, tid, lds, stw, ph); break;
+      case 32: grouped_x_body<Real, 32, DITHER>(v, tid, lds, stw, ph); break;
+      case 64: grouped_x_body<Real, 64, DITHER>(v, tid, lds, stw, ph); break;
+      case 128: grouped_x_body<Real, 128, DITHER>(v, tid, lds, stw, ph); break;
+      case 256: grouped_x_body<Real, 256, DITHER>(v, tid, lds, stw, ph); break;
+      case 512: grouped_x_body<Real, 512, DITHER>(v, tid, lds, stw, ph); break;
       default:
-        if constexpr (NMAX >= 1024) grouped_x_body<Real, 1024, DITHER>(v, tid, lds, stw, ph, rs);
+        if constexpr (NMAX >= 1024) grouped_x_body<Real, 1024, DITHER>(v, tid, lds, stw, ph);
         break;
     }
     if (a.g[g].tau_post != 0.0) {

@@ -36,7 +36,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
   __shared__ C lds[P * RowPad<N, T>::ROW];
   using TW = StagedTwiddles<Real, N, R>;
   using TE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
-  using TWA = std::conditional_t<PLAIN, WithRadix<StagedTwiddlesPlain<Real, N, R>>, TW>;
+  using TWA = std::conditional_t<PLAIN, StagedTwiddlesPlain<Real, N, R>, TW>;
   __shared__ TE stw[TW::SIZE > 0 ? TW::SIZE : 1];
   // phase tables of m = +1 (equal to m = -1, q enters as q m^2) and m = 0
   using PE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
@@ -63,15 +63,6 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
         ph[i] = gph[i];
     }
     __syncthreads();
-  }
-  // the twiddles (with the step's dithered radix constants in the plain form)
-  TWA twa{};
-  if constexpr (PLAIN) {
-    twa.tw.t = stw;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) twa.rc.d[k] = a.rc[k];
-  } else {
-    twa.t = stw;
   }
   C* psi = static_cast<C*>(a.psi);
   // out of place when a source field of the same layout is given
@@ -108,7 +99,7 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
     const double* prow = POT ? a.pot + (pid & (a.rows - 1)) * N : nullptr;
     if (a.tau_pre != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_pre), c0, c1, prow, a.tau_pre);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, twa, ph + (m == 1 ? N : 0));
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, TWA{stw}, ph + (m == 1 ? N : 0));
     if (a.tau_post != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_post), c0, c1, prow,
                                                                            a.tau_post);
     if (active) {
