@@ -592,6 +592,25 @@ def test_fp32_table_options(lib, mode):
         lib.Sim([g2], P1, dtype="c64").set_option(lib.OPT_FP32_TWIDDLES, 2)
 
 
+def test_dithered_tables_keep_the_norm_over_long_runs(lib):
+    """Over 5000 steps the per-sample norm of the complex64 field drifts much
+    less with dithered tables (their rounding does not repeat step after
+    step) than with compensated ones (measured 2.2e-7 against 7.4e-7)."""
+    grid = (2, (128, 128), 0.5, 4)
+    drift = {}
+    for opt in (lib.TWIDDLES_DITHERED, lib.TWIDDLES_COMPENSATED):
+        sim = lib.Sim([grid], P1, dtype="c64")
+        sim.set_option(lib.OPT_FP32_TWIDDLES, opt)
+        sim.init_wigner(5)
+        n0 = sim.observables()[:, 0]
+        for _ in range(5):
+            sim.step(1000, 0.02)
+        drift[opt] = float(np.max(np.abs(sim.observables()[:, 0] / n0 - 1)))
+        sim.close()
+    assert drift[lib.TWIDDLES_DITHERED] < 5e-7
+    assert drift[lib.TWIDDLES_DITHERED] < 0.6 * drift[lib.TWIDDLES_COMPENSATED]
+
+
 def test_autotune_choices_and_cache(lib, tmp_path):
     grids = [(2, (128, 64), 0.5, 4), (1, (1024,), 0.5, 8)]
     sim = lib.Sim(grids, P1, dtype="c64")
