@@ -43,10 +43,10 @@ __device__ __forceinline__ Real norm2(Cx<Real> a) { return a.re * a.re + a.im * 
 // ---------------------------------------------------------------------------
 // Table entries (twiddles, phase factors).  They are computed in FP64; the
 // single-precision path keeps each value as an unevaluated sum hi + lo of two
-// floats, so a multiply by a table value carries no systematic rounding of
-// the constant (only the rounding of the result, which is unbiased).  A
-// rounded constant would repeat the same relative error in every step and the
-// errors would add up linearly over a run.
+// floats.  A kernel either multiplies by hi + lo (compensated: no rounding of
+// the constant) or builds plain floats from them per step with dither_round.
+// A constant rounded once would repeat the same relative error in every step,
+// and the errors would add up linearly over a run.
 // ---------------------------------------------------------------------------
 template <typename Real>
 struct TabEntry;

@@ -52,7 +52,7 @@ struct SCfg {
 };
 
 constexpr int kStepVariants = 3;
-static_assert(kPlainTwiddles == kStepVariants, "plain-twiddle variants follow the compensated ones");
+static_assert(kPlainTwiddles == kStepVariants, "the dithered-table variants follow the compensated ones");
 
 // --------------------------------------------------------------------------
 // LDS views used by the FFT stages
