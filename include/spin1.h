@@ -253,6 +253,9 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   by error diffusion over the step index within the call so that the mean
  *   over steps tracks the FP64 value; a multiply costs half the compensated
  *   one, and the rounding of the constants does not add up step after step.
+ *   The dithering restarts with every call, so complex64 results of n steps
+ *   in one call and of the same steps split over several calls agree to
+ *   single precision but not bit for bit.
  *   SPIN1_TWIDDLES_COMPENSATED: hi+lo float pairs, so the constants carry no
  *   rounding of their own.  The radix constants of the in-register
  *   butterflies and the other passes use the compensated form either way.
