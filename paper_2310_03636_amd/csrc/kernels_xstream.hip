@@ -141,8 +141,13 @@ static hipError_t xpass_stream_p(hipStream_t st, const XPassArgs& a, int v) {
 template <typename Real, int N>
 static hipError_t xstream_n(hipStream_t st, const XPassArgs& a, int variant) {
   if constexpr (XCfg<N, Real>::STREAM) {
-    // a group with a trap potential runs the default variant
-    if (a.pot) return xpass_stream_v<Real, N, 0, false, true>(st, a);
+    // a group with a trap potential runs the default variant, with the table
+    // form the variant index asks for
+    if (a.pot) {
+      if constexpr (sizeof(Real) == 4)
+        if (variant >= kPlainTwiddles) return xpass_stream_v<Real, N, 0, true, true>(st, a);
+      return xpass_stream_v<Real, N, 0, false, true>(st, a);
+    }
     if constexpr (sizeof(Real) == 4)
       if (variant >= kPlainTwiddles) return xpass_stream_p<Real, N, true>(st, a, variant - kPlainTwiddles);
     return xpass_stream_p<Real, N, false>(st, a, variant % kPlainTwiddles);
