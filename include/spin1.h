@@ -140,6 +140,12 @@ SPIN1_API int spin1_set_potential(spin1_ctx* ctx, int32_t group, const double* v
  * half steps are merged inside the call; the field is at t + n dt on return. */
 SPIN1_API int spin1_step(spin1_ctx* ctx, int64_t n, double dt);
 
+/* Bring every bound field to its synchronized time.  spin1_step applies the
+ * closing half step R(dt/2) before it returns, so no half step is ever left
+ * pending and this call only validates the context (SPIN1_ESTATE if nothing
+ * is bound); it enqueues no device work. */
+SPIN1_API int spin1_sync_field(spin1_ctx* ctx);
+
 /* Per-sample shell means of |DFT F_perp(k)|^2 / N_sites for group `group`
  * (the sample average of these is S(t,k) of Sec. 2.1; a shell without modes
  * reports 0): bins_dev is a device array [S][spin1_num_bins] of double. */

@@ -795,6 +795,8 @@ int spin1_set_params(spin1_ctx* ctx, const spin1_params* p) {
   return SPIN1_OK;
 }
 
+int spin1_sync_field(spin1_ctx* ctx) { return check_ctx(ctx, true); }
+
 int spin1_step(spin1_ctx* ctx, int64_t n, double dt) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;

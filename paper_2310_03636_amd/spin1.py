@@ -23,7 +23,8 @@ OK, EINVAL, EUNSUPPORTED, EHIP, ESTATE, ENOMEM = 0, -1, -2, -3, -4, -5
 FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
-    "spin1_init_wigner", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_structure_factor",
+    "spin1_init_wigner", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_sync_field",
+    "spin1_structure_factor",
     "spin1_observables", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
     "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
@@ -83,6 +84,7 @@ def load():
         "spin1_set_params": (ctypes.c_int, [vp, pp]),
         "spin1_set_potential": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step": (ctypes.c_int, [vp, i64, f64]),
+        "spin1_sync_field": (ctypes.c_int, [vp]),
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step_observed": (ctypes.c_int, [vp, i64, f64, i32, vp]),
@@ -205,6 +207,10 @@ def set_potential(ctx, group, v_ptr):
 
 def step(ctx, n, dt):
     _check(load().spin1_step(ctx, int(n), float(dt)))
+
+
+def sync_field(ctx):
+    _check(load().spin1_sync_field(ctx))
 
 
 def structure_factor(ctx, group, bins_ptr):

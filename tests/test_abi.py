@@ -82,6 +82,7 @@ def test_null_context_calls_fail_cleanly(abi):
     assert lib.spin1_set_option(None, 0, 1) == abi.EINVAL
     assert lib.spin1_profile_enable(None, 1) == abi.EINVAL
     assert lib.spin1_set_potential(None, 0, None) == abi.EINVAL
+    assert lib.spin1_sync_field(None) == abi.EINVAL
     assert lib.spin1_step_observed(None, 1, 0.01, 0, None) == abi.EINVAL
     assert lib.spin1_transverse_spin(None, 0, None) == abi.EINVAL
     assert lib.spin1_spin_texture(None, 0, None) == abi.EINVAL
