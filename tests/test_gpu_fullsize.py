@@ -82,6 +82,24 @@ def test_3d_256_8_samples_full_size_invariants(lib):
     assert err < 1e-4, err
 
 
+@pytest.mark.timeout(600)
+def test_3d_256_8_samples_full_size_last_sample_against_oracle(lib):
+    """One split step of the full 256^3 x 8 batch in the benchmark's launch
+    configuration (autotuned variants, captured graph); its last sample
+    against the oracle run on that sample alone (16.8M sites, about a minute
+    of CPU)."""
+    p3 = dict(c0=1.0, c1=-0.05, q=0.025, n0=1.0, wigner_var=0.5)
+    g = (3, (256, 256, 256), 0.5, 8)
+    sim = lib.Sim([g], p3, dtype="c64")
+    sim.init_wigner(1003)
+    sim.autotune(reps=1)
+    sim.step(1, 0.02)
+    got = sim.field_tensor(0)[7].cpu().numpy().astype(np.complex128)
+    sim.close()
+    ref = oracle_samples(1003, g, p3, 0, [7], 1, 0.02)[0]
+    assert rel(got, ref) < 1e-5
+
+
 def test_1d_4096_250_runs_fp64_full_size(lib):
     """The paper's production shape: 250 runs of 1D L = 4096 in double precision."""
     g = (1, (4096,), 0.5, 250)
