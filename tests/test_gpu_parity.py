@@ -219,6 +219,27 @@ def test_zero_steps_is_identity(lib):
     assert np.array_equal(sim.fields()[0], psi0)
 
 
+def test_sync_field_leaves_the_synchronized_field_alone(lib):
+    """Step calls end at a synchronized time, so spin1_sync_field has nothing
+    to apply: it rejects an unbound context and leaves a stepped field bit for
+    bit as it was."""
+    fresh = lib.create(lib.C128)
+    with pytest.raises(lib.Spin1Error) as err:
+        lib.sync_field(fresh)
+    assert err.value.code == lib.ESTATE
+    lib.destroy(fresh)
+    grid = (2, (32, 16), 0.5, 2)
+    og = O.Grid(2, (32, 16), 0.5, 2)
+    psi0 = random_field(10, og.shape)
+    sim = run_gpu(lib, grid, P1, "c128", psi0=psi0, nsteps=3, dt=0.01)
+    before = sim.fields()[0]
+    lib.sync_field(sim.ctx)
+    sim.synchronize()
+    assert np.array_equal(sim.fields()[0], before)
+    ref = O.evolve(psi0, 3, 0.01, oparams(P1), og)
+    assert rel(before, ref) < 1e-12
+
+
 def test_quench_set_params(lib):
     grid = (1, (128,), 0.5, 2)
     og = O.Grid(1, (128,), 0.5, 2)
