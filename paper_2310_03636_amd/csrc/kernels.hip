@@ -57,7 +57,7 @@ int spass_tx(int n, bool dbl) { return dbl ? spass_tx_t<double>(n) : spass_tx_t<
 // --------------------------------------------------------------------------
 // x-pass: contiguous pencils, all 3 components of each site in one thread
 // --------------------------------------------------------------------------
-template <typename Real, int N, int MODE>
+template <typename Real, int N, int MODE, bool STAGE_TW = false>
 __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a) {
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real>::R, T = XCfg<N, Real>::T, P = XCfg<N, Real>::P;
@@ -70,6 +70,23 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
   const int64_t row = active ? pid - s * a.rows : 0;
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
   const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
+  // STAGE_TW (long pencils, at most one workgroup per CU): the twiddles are
+  // staged in LDS in stage order first.  Read from global memory, every stage
+  // of every transform waits for its twiddle loads, and with one workgroup per
+  // CU nothing covers those waits.  With more workgroups than CUs the larger
+  // LDS footprint costs more (fewer resident workgroups) than it saves.
+  using STW = StagedTwiddles<Real, N, R>;
+  __shared__ TabEntry<Real> stw[STAGE_TW ? STW::SIZE : 1];
+  if constexpr (STAGE_TW) {
+    for (int i = threadIdx.x; i < STW::SIZE; i += blockDim.x) stw[i] = tw[STW::exponent(i)];
+    __syncthreads();
+  }
+  const auto twa = [&] {
+    if constexpr (STAGE_TW)
+      return STW{stw};
+    else
+      return tw;
+  }();
   const int64_t off = s * 3 * a.sites + row * N + t;
   C* base = static_cast<C*>(a.psi) + off;
   const C* in = (MODE == MODE_STEP && a.src) ? static_cast<const C*>(a.src) + off : base;
@@ -93,21 +110,21 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
         site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc, prow ? prow[t + e * T] : 0.0);
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        fft_pencil<Real, N, R>(v[m], t, L, tw);
+        fft_pencil<Real, N, R>(v[m], t, L, twa);
 #pragma unroll
         for (int e = 0; e < R; ++e) {
           const double kk = a.kscale * double(signed_k<N>(t + e * T));
           acc[3] += 0.5 * kk * kk * double(norm2(v[m][e]));
           v[m][e] = conj(mul_tab(v[m][e], ph[m * N + t + e * T]));
         }
-        fft_pencil<Real, N, R>(v[m], t, L, tw);
+        fft_pencil<Real, N, R>(v[m], t, L, twa);
 #pragma unroll
         for (int e = 0; e < R; ++e) v[m][e] = conj(v[m][e]);
       }
       acc[3] *= 1.0 / double(N);
     } else {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph + m * N);
+      for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, twa, ph + m * N);
     }
     if (a.tau_post != 0.0) local_update_sites<Real, R, T, POT_IF_SET>(v, t, Real(a.tau_post), c0, c1, prow, a.tau_post);
     if (active) {
@@ -133,7 +150,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
     // kinetic phase alone (the m = 0 row of the x table; q sits in D)
     const TabEntry<Real>* ph0 = static_cast<const TabEntry<Real>*>(a.ph) + N;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, tw, ph0);
+    for (int m = 0; m < 3; ++m) fft_phase_ifft<Real, N, R>(v[m], t, L, twa, ph0);
     if (a.tau_post != 0.0) local_all(a.tau_post);
     if (active) {
 #pragma unroll
@@ -148,7 +165,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
       site_sums(v[0][e], v[1][e], v[2][e], a.c0, a.c1, a.q, acc, prow ? prow[t + e * T] : 0.0);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      fft_pencil<Real, N, R>(v[m], t, L, tw);
+      fft_pencil<Real, N, R>(v[m], t, L, twa);
 #pragma unroll
       for (int e = 0; e < R; ++e) {
         const double kk = a.kscale * double(signed_k<N>(t + e * T));
@@ -163,7 +180,7 @@ __global__ __launch_bounds__((XCfg<N, Real>::THREADS)) void k_xpass(XPassArgs a)
     C f[R];
 #pragma unroll
     for (int e = 0; e < R; ++e) f[e] = scale(cmulc(v[0][e], v[1][e]) + cmulc(v[1][e], v[2][e]), r2);
-    fft_pencil<Real, N, R>(f, t, L, tw);
+    fft_pencil<Real, N, R>(f, t, L, twa);
     if (active) {
       const int64_t o = (s * a.rows + row) * N + t;
       if constexpr (MODE == MODE_SF) {
@@ -191,6 +208,13 @@ static hipError_t xpass_n(hipStream_t st, const XPassArgs& a, int variant) {
   } else {
     constexpr int P = XCfg<N, Real>::P;
     const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
+    if constexpr (N >= 2048) {
+      if (blocks <= device_cus()) {
+        hipLaunchKernelGGL((k_xpass<Real, N, MODE, true>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0,
+                           st, a);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
     return hipGetLastError();
   }

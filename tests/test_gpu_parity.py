@@ -79,6 +79,33 @@ def test_one_step_1d_all_sizes(lib, n, per_launch):
         assert rel(sim.fields()[0], ref) < tol, dtype
 
 
+@pytest.mark.parametrize("n,samples", [(2048, 300), (4096, 300), (2048, 40), (4096, 40)])
+def test_long_pencils_both_table_forms(lib, n, samples):
+    """Pencils of 2048 and 4096 points: up to one workgroup per CU the x-pass
+    stages its twiddles in LDS, beyond that it reads them from global memory;
+    both forms, in every mode a step and the observables use, against the
+    oracle."""
+    grid = (1, (n,), 0.5, samples)
+    og = O.Grid(1, (n,), 0.5, samples)
+    psi0 = random_field(n + 7, og.shape, noise=0.4)
+    ref = O.evolve(psi0, 2, 0.01, oparams(P1), og)
+    for dtype, tol in (("c128", 1e-12), ("c64", 5e-6)):
+        sim = lib.Sim([grid], P1, dtype=dtype)
+        sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 1)
+        sim.set_fields([psi0])
+        sim.step(2, 0.01)
+        assert rel(sim.fields()[0], ref) < tol, dtype
+        obs = sim.observables()
+        ref_obs = O.observables(ref, oparams(P1), og)
+        rt = 1e-10 if dtype == "c128" else 1e-5
+        assert np.allclose(obs[:, 0::2], ref_obs[:, 0::2], rtol=rt), dtype  # N, E
+        assert np.abs(obs[:, 1] - ref_obs[:, 1]).max() < rt * ref_obs[:, 0].max(), dtype  # F_z, a difference
+        _, _, _, _, per = sim.structure_factor()
+        ref_sk = O.structure_factor(ref, og)
+        assert rel(per, ref_sk) < (1e-10 if dtype == "c128" else 2e-5), dtype
+        sim.close()
+
+
 @pytest.mark.parametrize("n", [8, 16, 64, 256, 512, 1024, 2048, 4096])
 def test_multi_step_1d_chunks_match_oracle(lib, n):
     """23 steps as launches of 7, 7, 7 and 2 steps (first opens, last closes
