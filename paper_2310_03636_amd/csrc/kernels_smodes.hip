@@ -24,18 +24,33 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
   C* base = static_cast<C*>(a.psi) + off;
   ColLds<Real, TX> L{lds + c};
   const TabEntry<Real>* tw = static_cast<const TabEntry<Real>*>(a.tw);
+  // the step-log pass stages its twiddles in LDS in stage order (read from
+  // global memory, every stage waits for its twiddle loads)
+  constexpr bool STAGE_TW = MODE == MODE_STEP_LOG && N > R;
+  using STW = StagedTwiddles<Real, N, R>;
+  __shared__ TabEntry<Real> stw[STAGE_TW ? STW::SIZE : 1];
+  if constexpr (STAGE_TW) {
+    for (int i = threadIdx.x; i < STW::SIZE; i += blockDim.x) stw[i] = tw[STW::exponent(i)];
+    __syncthreads();
+  }
+  const auto twa = [&] {
+    if constexpr (STAGE_TW)
+      return STW{stw};
+    else
+      return tw;
+  }();
 
   C v[R];
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = base[int64_t(t + e * T) * a.sa];
 
   if constexpr (MODE == MODE_STEP) {
-    fft_phase_ifft<Real, N, R>(v, t, L, tw, static_cast<const TabEntry<Real>*>(a.ph));
+    fft_phase_ifft<Real, N, R>(v, t, L, twa, static_cast<const TabEntry<Real>*>(a.ph));
 #pragma unroll
     for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
   } else if constexpr (MODE == MODE_STEP_LOG) {
     const TabEntry<Real>* ph = static_cast<const TabEntry<Real>*>(a.ph);
-    fft_pencil<Real, N, R>(v, t, L, tw);
+    fft_pencil<Real, N, R>(v, t, L, twa);
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < R; ++e) {
@@ -43,14 +58,14 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
       acc += 0.5 * kk * kk * double(norm2(v[e]));
       v[e] = conj(mul_tab(v[e], ph[t + e * T]));
     }
-    fft_pencil<Real, N, R>(v, t, L, tw);
+    fft_pencil<Real, N, R>(v, t, L, twa);
 #pragma unroll
     for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = conj(v[e]);
     acc *= 1.0 / double(N);
     const double tot = block_sum(acc, reinterpret_cast<double*>(lds));
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
   } else if constexpr (MODE == MODE_MEASURE) {
-    fft_pencil<Real, N, R>(v, t, L, tw);
+    fft_pencil<Real, N, R>(v, t, L, twa);
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < R; ++e) {
@@ -61,11 +76,11 @@ __global__ __launch_bounds__((SCfg<N, Real>::THREADS)) void k_spass(SPassArgs a)
     const double tot = block_sum(acc, reinterpret_cast<double*>(lds));
     if (threadIdx.x == 0) a.part[blockIdx.x] = tot;
   } else if constexpr (MODE == MODE_SF) {
-    fft_pencil<Real, N, R>(v, t, L, tw);
+    fft_pencil<Real, N, R>(v, t, L, twa);
 #pragma unroll
     for (int e = 0; e < R; ++e) base[int64_t(t + e * T) * a.sa] = v[e];
   } else {
-    fft_pencil<Real, N, R>(v, t, L, tw);
+    fft_pencil<Real, N, R>(v, t, L, twa);
     Real* out = static_cast<Real*>(a.out) + off;
     const Real ps = Real(a.power_scale);
 #pragma unroll
