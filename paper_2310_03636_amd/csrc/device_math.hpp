@@ -434,6 +434,59 @@ __device__ __forceinline__ void sinc_cos_from_square(float u, float* sc, float* 
   }
 }
 
+// Double precision: the same forms with series to u^8 (remainder below 1e-17
+// relative for |y| <= pi/4) and the library sincos, out of line, beyond.
+__device__ __forceinline__ double sinc_series(double u) {
+  double p = fma(u, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);
+  p = fma(u, p, 1.0 / 6227020800.0);
+  p = fma(u, p, -1.0 / 39916800.0);
+  p = fma(u, p, 1.0 / 362880.0);
+  p = fma(u, p, -1.0 / 5040.0);
+  p = fma(u, p, 1.0 / 120.0);
+  p = fma(u, p, -1.0 / 6.0);
+  return fma(u, p, 1.0);
+}
+__device__ __forceinline__ double cos_series(double u) {
+  double q = fma(u, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);
+  q = fma(u, q, 1.0 / 479001600.0);
+  q = fma(u, q, -1.0 / 3628800.0);
+  q = fma(u, q, 1.0 / 40320.0);
+  q = fma(u, q, -1.0 / 720.0);
+  q = fma(u, q, 1.0 / 24.0);
+  q = fma(u, q, -0.5);
+  return fma(u, q, 1.0);
+}
+struct SinCosD {
+  double s, c;
+};
+__device__ __noinline__ SinCosD sincos_lib(double y) {
+  SinCosD r;
+  sincos(y, &r.s, &r.c);
+  return r;
+}
+__device__ __forceinline__ void sincos_small(double y, double* s, double* c) {
+  const double u = y * y;
+  if (u < 0.61685027506808491) {  // |y| < pi/4
+    *s = y * sinc_series(u);
+    *c = cos_series(u);
+  } else {
+    const SinCosD r = sincos_lib(y);
+    *s = r.s;
+    *c = r.c;
+  }
+}
+__device__ __forceinline__ void sinc_cos_from_square(double u, double* sc, double* c) {
+  if (u < 0.61685027506808491) {
+    *sc = sinc_series(u);
+    *c = cos_series(u);
+  } else {
+    const double y = sqrt(u);
+    const SinCosD r = sincos_lib(y);
+    *c = r.c;
+    *sc = r.s / y;
+  }
+}
+
 template <typename Real>
 __device__ __forceinline__ void apply_M(const Cx<Real>* a, Cx<Real>* out, Cx<Real> g, Real fz) {
   out[0] = scale(a[0], fz) + cmulc(g, a[1]);
@@ -446,30 +499,15 @@ __device__ __forceinline__ void apply_M(const Cx<Real>* a, Cx<Real>* out, Cx<Rea
 template <typename Real>
 __device__ __forceinline__ void rotation_coeffs(Real f2, Real theta, Real* s, Real* c) {
   Real sc, ch;
-  if constexpr (sizeof(Real) == 4) {
-    // f2 times a factor that is the same for every site (kept out of site loops)
-    sinc_cos_from_square(f2 * (Real(0.25) * theta * theta), &sc, &ch);
-  } else {
-    const Real half = Real(0.5) * sqrt(f2) * theta;
-    Real sh;
-    sincos(half, &sh, &ch);
-    if (fabs(half) < 1e-3) {
-      const Real h2 = half * half;
-      sc = Real(1) - h2 * (Real(1) / Real(6)) + h2 * h2 * (Real(1) / Real(120));
-    } else {
-      sc = sh / half;
-    }
-  }
+  // f2 times a factor that is the same for every site (kept out of site loops)
+  sinc_cos_from_square(f2 * (Real(0.25) * theta * theta), &sc, &ch);
   *s = theta * (sc * ch);
   *c = (Real(-0.5) * theta * theta) * (sc * sc);
 }
 
 template <typename Real>
 __device__ __forceinline__ void angle_sincos(Real a, Real* sn, Real* cs) {
-  if constexpr (sizeof(Real) == 4)
-    sincos_small(a, sn, cs);
-  else
-    sincos(a, sn, cs);
+  sincos_small(a, sn, cs);
 }
 
 // The phase angle V tau of a trap potential for a kernel in precision Real:
