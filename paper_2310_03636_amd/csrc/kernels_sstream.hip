@@ -25,7 +25,8 @@ template <typename Real, int N, int V, bool PLAIN>
 __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
   constexpr int R = SCfg<N, Real, V>::R, T = SCfg<N, Real, V>::T, TX = SCfg<N, Real, V>::TX;
-  __shared__ C lds[N * ColLds<Real, TX>::PITCH];
+  constexpr int PITCH = SCfg<N, Real, V>::PITCH;
+  __shared__ C lds[N * PITCH];
   using TE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
   __shared__ TE tw[N];
   using PE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
@@ -33,7 +34,7 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
   const int c = threadIdx.x % TX;
   const int t = threadIdx.x / TX;
   const int64_t tiles = a.inner / TX;
-  ColLds<Real, TX> L{lds + c};
+  ColLds<Real, TX, PITCH> L{lds + c};
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph);

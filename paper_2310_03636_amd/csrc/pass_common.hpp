@@ -49,6 +49,9 @@ struct SCfg {
   static constexpr int TX = TX1 * T > 1024 ? 1024 / T : TX1;
   static constexpr int THREADS = TX * T;
   static constexpr bool STREAM = true;
+  // FP64 columns of 512 on 8-column tiles: rows unpadded, so that two
+  // workgroups fit in LDS (77.8 instead of 86 KB each)
+  static constexpr int PITCH = (sizeof(Real) == 8 && N == 512 && TX == 8) ? TX : (TX >= 16 ? TX : TX + 1);
 };
 
 constexpr int kStepVariants = 3;
@@ -92,9 +95,9 @@ struct RowLds {
 
 // Column tiles: element i of column c at i * (TX + 1) + c; the odd row pitch
 // spreads rows that differ by a power of two over different banks.
-template <typename Real, int TX>
+template <typename Real, int TX, int PITCH_ = (TX >= 16 ? TX : TX + 1)>
 struct ColLds {
-  static constexpr int PITCH = TX >= 16 ? TX : TX + 1;
+  static constexpr int PITCH = PITCH_;
   Cx<Real>* col;
   __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * PITCH] = v; }
   __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * PITCH]; }
