@@ -315,22 +315,36 @@ def offdiag_matrix(a, b):
 
 
 def paper_step(psi, dt, p, grid, V=None):
-    """One step of the literal Lie-order scheme of Eqs. (3)-(5).
+    """One step of the literal Lie-order scheme of Eqs. (3)-(5): the kinetic
+    phase of Eq. (3) (``paper_kinetic``), then the diagonal phases of Eq. (4)
+    with the densities of the field they act on (``paper_diagonal``), then the
+    off-diagonal mixing of Eq. (5) with predictor-averaged couplings
+    (``paper_offdiagonal``)."""
+    psi1 = paper_kinetic(psi, dt, grid)
+    psi2 = paper_diagonal(psi1, dt, p, V)
+    return paper_offdiagonal(psi2, dt, p.c1)
 
-    (3) kinetic phase exp(-i dt |k|^2/2) in Fourier space;
-    (4) diagonal phase exp(-i f_m dt) with f_m the diagonal of the bracket of
-        Eq. (2) apart from the kinetic term, densities taken from psi';
-    (5) off-diagonal mixing with the predictor-averaged couplings
-        a = [psi_-1^* psi_0 + tpsi_-1^* tpsi_0]/2, b = [psi_0^* psi_1 + tpsi_0^* tpsi_1]/2,
-        tpsi = psi'' - i c1 dt S(a0, b0) psi''.
-    """
+
+def paper_kinetic(psi, dt, grid):
+    """Eq. (3): every component goes to IFFT[exp(-i dt |k|^2 / 2) FFT psi_m].
+    No q here: the paper's scheme keeps q in the diagonal phases of Eq. (4)."""
     k2 = k_squared(grid)
-    c0, c1, q = p.c0, p.c1, p.q
-    psi1 = np.empty_like(psi, dtype=np.complex128)
+    out = np.empty_like(psi, dtype=np.complex128)
     for c in range(3):
         spec = fftn_last(psi[:, c], grid.dim)
-        psi1[:, c] = fftn_last(spec * np.exp(-1j * 0.5 * k2 * dt), grid.dim, inverse=True)
-    dens = np.abs(psi1) ** 2
+        out[:, c] = fftn_last(spec * np.exp(-1j * 0.5 * k2 * dt), grid.dim, inverse=True)
+    return out
+
+
+def paper_diagonal_rates(psi, p, V=None):
+    """The rates f_m of Eq. (4), evaluated with the densities of ``psi``:
+    the diagonal of the bracket of Eq. (2) without the kinetic term,
+        f_{+1} = q + (c0 + c1) rho - 2 c1 |psi_{-1}|^2,
+        f_0    =     (c0 + c1) rho -   c1 |psi_0|^2,
+        f_{-1} = q + (c0 + c1) rho - 2 c1 |psi_{+1}|^2,
+    plus V_m(x_j) (the same for every m).  Real array of the field's shape."""
+    c0, c1, q = p.c0, p.c1, p.q
+    dens = np.abs(psi) ** 2
     rho = np.sum(dens, axis=1)
     f_p = q + (c0 + c1) * rho - 2.0 * c1 * dens[:, 2]
     f_0 = (c0 + c1) * rho - c1 * dens[:, 1]
@@ -338,10 +352,29 @@ def paper_step(psi, dt, p, grid, V=None):
     diag = np.stack([f_p, f_0, f_m], axis=1)
     if V is not None:  # V_m(x_j) of Eq. (4), the same for every m
         diag = diag + np.asarray(V, dtype=np.float64)[None, None]
-    psi2 = psi1 * np.exp(-1j * diag * dt)
-    a0 = np.conj(psi2[:, 2]) * psi2[:, 1]
-    b0 = np.conj(psi2[:, 1]) * psi2[:, 0]
-    sv = np.moveaxis(psi2, 1, -1)
+    return diag
+
+
+def paper_diagonal(psi, dt, p, V=None):
+    """Eq. (4): psi_m -> exp(-i f_m dt) psi_m with f_m = paper_diagonal_rates(psi)
+    (the densities of the field being multiplied)."""
+    return psi * np.exp(-1j * paper_diagonal_rates(psi, p, V) * dt)
+
+
+def paper_couplings(psi):
+    """Couplings of the off-diagonal part S(a, b) of Eq. (2)'s matrix at every
+    site (Eq. (5) and the definitions below it): a = psi_{-1}^* psi_0 and
+    b = psi_0^* psi_{+1}."""
+    return np.conj(psi[:, 2]) * psi[:, 1], np.conj(psi[:, 1]) * psi[:, 0]
+
+
+def paper_offdiagonal(psi, dt, c1):
+    """Eq. (5): psi -> M(a, b) psi, with M the matrix of Eq. (5) at angle
+    theta = c1 dt and couplings averaged over the field and a one-step
+    predictor: a0, b0 = paper_couplings(psi), tpsi = psi - i c1 dt S(a0, b0) psi,
+    a = [a0 + tpsi_{-1}^* tpsi_0] / 2, b = [b0 + tpsi_0^* tpsi_{+1}] / 2."""
+    a0, b0 = paper_couplings(psi)
+    sv = np.moveaxis(psi, 1, -1)
     pred = sv - 1j * c1 * dt * np.einsum("...ij,...j->...i", offdiag_matrix(a0, b0), sv)
     a = 0.5 * (a0 + np.conj(pred[..., 2]) * pred[..., 1])
     b = 0.5 * (b0 + np.conj(pred[..., 1]) * pred[..., 0])
@@ -486,6 +519,7 @@ __all__ = [
     "Grid", "Params", "spin_matrices", "density", "spin_vector", "f_perp",
     "wavenumbers", "k_squared", "init_wigner", "local_hamiltonian", "local_flow",
     "kinetic_zeeman", "strang_step", "evolve", "eq5_matrix", "offdiag_matrix",
-    "paper_step", "observables", "bin_index", "num_bins", "bin_counts", "bin_k",
+    "paper_step", "paper_kinetic", "paper_diagonal_rates", "paper_diagonal", "paper_couplings",
+    "paper_offdiagonal", "observables", "bin_index", "num_bins", "bin_counts", "bin_k",
     "structure_factor", "sample_mean_se", "gpe_rhs_printed", "fft_field", "fft_axis",
 ]
