@@ -114,6 +114,22 @@ SPIN1_API int spin1_bind(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_gro
 SPIN1_API int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
                       const spin1_params* p, void* const* psi_dev, void* workspace_dev);
 
+/* spin1_init_wigner for one shard of a larger ensemble.  The Wigner samples
+ * are independent runs (Sec. 2.2: many runs per GPU, and runs spread over
+ * several GPUs), so an ensemble can be split by sample: sample s of group i
+ * here is sample first_sample[i] + s of the whole ensemble, and its noise
+ * comes from the generator counter (site, component, first_sample[i] + s, i)
+ * with key (seed, 0).  Contexts that bind the same groups in the same order
+ * with disjoint ranges of samples therefore produce exactly the fields (and,
+ * being per sample, the shell means and observables) that one context over
+ * the whole ensemble produces for those samples.  first_sample: host array of
+ * n_groups values >= 0, or NULL for all zeros (then this is
+ * spin1_init_wigner).  Errors as spin1_init_wigner, and SPIN1_EINVAL for a
+ * negative or overflowing offset (checked before anything is bound). */
+SPIN1_API int spin1_init_wigner_shard(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
+                                      const int64_t* first_sample, const spin1_params* p, void* const* psi_dev,
+                                      void* workspace_dev);
+
 /* Replace the couplings between steps (a quench of q, Sec. 2.1, Fig. 1). */
 SPIN1_API int spin1_set_params(spin1_ctx* ctx, const spin1_params* p);
 

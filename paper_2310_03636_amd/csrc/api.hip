@@ -771,18 +771,31 @@ int spin1_bind(spin1_ctx* ctx, const spin1_grid* groups, int32_t n_groups, const
   return bind_impl(ctx, groups, n_groups, p, psi_dev, workspace_dev);
 }
 
-int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
-                      const spin1_params* p, void* const* psi_dev, void* workspace_dev) {
-  int rc = bind_impl(ctx, groups, n_groups, p, psi_dev, workspace_dev);
+int spin1_init_wigner_shard(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
+                            const int64_t* first_sample, const spin1_params* p, void* const* psi_dev,
+                            void* workspace_dev) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  if (first_sample && n_groups > 0 && groups)  // checked before the bind changes any state
+    for (int32_t i = 0; i < n_groups; ++i)
+      if (first_sample[i] < 0 || first_sample[i] > (int64_t(1) << 62) - groups[i].samples)
+        return fail(SPIN1_EINVAL, "first_sample[%d] = %lld is out of range", i, (long long)first_sample[i]);
+  rc = bind_impl(ctx, groups, n_groups, p, psi_dev, workspace_dev);
   if (rc) return rc;
   for (size_t i = 0; i < ctx->groups.size(); ++i) {
     const GroupState& G = ctx->groups[i];
     Prof pr(ctx, SPIN1_K_OTHER);
+    const uint64_t first = first_sample ? uint64_t(first_sample[i]) : 0;
     const hipError_t e =
-        launch_init(ctx->stream, ctx->dbl, G.psi, G.geo, seed, uint64_t(i), ctx->p.n0, ctx->p.wigner_var);
+        launch_init(ctx->stream, ctx->dbl, G.psi, G.geo, seed, uint64_t(i), first, ctx->p.n0, ctx->p.wigner_var);
     if (e != hipSuccess) return hip_fail(e, "init kernel");
   }
   return SPIN1_OK;
+}
+
+int spin1_init_wigner(spin1_ctx* ctx, uint64_t seed, const spin1_grid* groups, int32_t n_groups,
+                      const spin1_params* p, void* const* psi_dev, void* workspace_dev) {
+  return spin1_init_wigner_shard(ctx, seed, groups, n_groups, nullptr, p, psi_dev, workspace_dev);
 }
 
 int spin1_set_params(spin1_ctx* ctx, const spin1_params* p) {

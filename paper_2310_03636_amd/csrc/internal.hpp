@@ -90,8 +90,10 @@ struct SPassArgs {
 
 hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, int ncomp, double dt, double q,
                          double dx);
+// first_sample: index of the field's sample 0 in the whole ensemble (the
+// generator's sample counter is first_sample + s)
 hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
-                       double n0, double wigner_var);
+                       uint64_t first_sample, double n0, double wigner_var);
 // variant: step-pass variant index (0 = default), ignored by the other modes
 // step-pass variant offset selecting the dithered plain FP32 tables (twiddles and phases)
 constexpr int kPlainTwiddles = 3;

@@ -134,7 +134,7 @@ __global__ void k_tables(TabEntry<Real>* ph, TabEntry<Real>* tw, int n, int ncom
 // --------------------------------------------------------------------------
 template <typename Real>
 __global__ __launch_bounds__(256) void k_init(Cx<Real>* psi, int S, int64_t sites, uint64_t seed, uint64_t group,
-                                              double amp, double sqrt_n0) {
+                                              uint64_t first_sample, double amp, double sqrt_n0) {
   const int64_t total = int64_t(S) * 3 * sites;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
     const int64_t x = i % sites;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_init(Cx<Real>* psi, int S, int64_t site
     U64x4 ctr;
     ctr.v[0] = uint64_t(x);
     ctr.v[1] = uint64_t(c);
-    ctr.v[2] = uint64_t(s);
+    ctr.v[2] = uint64_t(s) + first_sample;  // the sample's index in the whole ensemble
     ctr.v[3] = group;
     const U64x4 r = philox4x64_10(ctr, seed, 0ull);
     const double u1 = open_unit(r.v[0]), u2 = open_unit(r.v[1]);
@@ -393,17 +393,17 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
   return hipGetLastError();
 }
 
-hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group, double n0,
-                       double wigner_var) {
+hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint64_t seed, uint64_t group,
+                       uint64_t first_sample, double n0, double wigner_var) {
   const double cell = g.dim == 1 ? g.dx : (g.dim == 2 ? g.dx * g.dx : g.dx * g.dx * g.dx);
   const double amp = sqrt(wigner_var / (2.0 * cell));
   const unsigned blocks = grid_for(int64_t(g.S) * 3 * g.sites, 256);
   if (dbl)
     hipLaunchKernelGGL(k_init<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), g.S, g.sites,
-                       seed, group, amp, sqrt(n0));
+                       seed, group, first_sample, amp, sqrt(n0));
   else
     hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), g.S, g.sites,
-                       seed, group, amp, sqrt(n0));
+                       seed, group, first_sample, amp, sqrt(n0));
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ OK, EINVAL, EUNSUPPORTED, EHIP, ESTATE, ENOMEM = 0, -1, -2, -3, -4, -5
 FUNCTIONS = [
     "spin1_create", "spin1_destroy", "spin1_check_grid", "spin1_field_bytes",
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
-    "spin1_init_wigner", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_sync_field",
+    "spin1_init_wigner", "spin1_init_wigner_shard", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_sync_field",
     "spin1_structure_factor",
     "spin1_observables", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
     "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
@@ -81,6 +81,8 @@ def load():
         "spin1_bin_counts": (ctypes.c_int, [gp, ctypes.POINTER(i64)]),
         "spin1_bind": (ctypes.c_int, [vp, gp, i32, pp, ctypes.POINTER(vp), vp]),
         "spin1_init_wigner": (ctypes.c_int, [vp, ctypes.c_uint64, gp, i32, pp, ctypes.POINTER(vp), vp]),
+        "spin1_init_wigner_shard": (ctypes.c_int, [vp, ctypes.c_uint64, gp, i32, ctypes.POINTER(i64), pp,
+                                                   ctypes.POINTER(vp), vp]),
         "spin1_set_params": (ctypes.c_int, [vp, pp]),
         "spin1_set_potential": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step": (ctypes.c_int, [vp, i64, f64]),
@@ -196,6 +198,17 @@ def init_wigner(ctx, seed, grids, params, psi_ptrs, workspace_ptr):
                                     _ptr_array(psi_ptrs), ctypes.c_void_p(int(workspace_ptr))))
 
 
+def init_wigner_shard(ctx, seed, grids, first_samples, params, psi_ptrs, workspace_ptr):
+    """init_wigner with sample s of group i numbered first_samples[i] + s in the
+    generator's counter (first_samples None: all zeros)."""
+    arr, n = _grid_array(grids)
+    offs = None
+    if first_samples is not None:
+        offs = (ctypes.c_int64 * n)(*[int(v) for v in first_samples])
+    _check(load().spin1_init_wigner_shard(ctx, ctypes.c_uint64(int(seed)), arr, n, offs, ctypes.byref(params),
+                                          _ptr_array(psi_ptrs), ctypes.c_void_p(int(workspace_ptr))))
+
+
 def set_params(ctx, params):
     _check(load().spin1_set_params(ctx, ctypes.byref(params)))
 
@@ -301,9 +314,14 @@ class Sim:
     dtype: "c64" or "c128".  Torch supplies the device memory and a stream
     of its own (default priority); every torch operation of this object runs
     on that stream, so the library's work and torch's copies stay ordered.
-    Methods that return host arrays synchronise that stream.  ``psi`` holds
-    the device tensors themselves; work on them from another stream only
-    after ``synchronize()`` (or take them through ``field_tensor``).
+    Ordering against the caller: every method first makes this object's
+    stream wait for the caller's current stream (so device tensors the caller
+    produced there, and the caller's own work on ``psi``, are complete before
+    the library reads them), tensors of the caller read here are marked as in
+    use on this object's stream, and device tensors handed back without
+    synchronising are ordered the other way round (the caller's current
+    stream waits for this object's stream).  Methods that return host arrays
+    synchronise.  ``psi`` holds the device tensors themselves.
     """
 
     def __init__(self, groups, params, dtype="c64", device="cuda:0"):
@@ -343,6 +361,25 @@ class Sim:
     def _ptrs(self):
         return [p.data_ptr() for p in self.psi]
 
+    def _follow_caller(self):
+        """This object's stream waits for the caller's current stream."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _borrow(self, t):
+        """A caller's device tensor that work on this object's stream reads:
+        keep its memory from being reused before that work is done."""
+        if isinstance(t, self.torch.Tensor) and t.is_cuda:
+            t.record_stream(self.stream)
+
+    def _hand_back(self, t):
+        """A device tensor produced on this object's stream and returned
+        without synchronising: the caller's current stream waits for it."""
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            t.record_stream(cur)
+        return t
+
     def synchronize(self):
         self.stream.synchronize()
 
@@ -350,8 +387,16 @@ class Sim:
         for group, v in self.potentials.items():
             set_potential(self.ctx, group, v.data_ptr())
 
-    def init_wigner(self, seed):
-        init_wigner(self.ctx, seed, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
+    def init_wigner(self, seed, first_samples=None):
+        """Wigner initial state; first_samples (one offset per group, or None)
+        numbers this object's samples within a larger ensemble
+        (spin1_init_wigner_shard)."""
+        self._follow_caller()
+        if first_samples is None:
+            init_wigner(self.ctx, seed, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
+        else:
+            init_wigner_shard(self.ctx, seed, self.grids, first_samples, self.params, self._ptrs(),
+                              self.ws.data_ptr())
         self.bound = True
         self._rebind_potentials()
 
@@ -366,6 +411,8 @@ class Sim:
                 set_potential(self.ctx, group, 0)
             return
         shape = _spatial(self.grids[group])
+        self._follow_caller()
+        self._borrow(V)
         with torch.cuda.stream(self.stream):
             v = torch.as_tensor(np.asarray(V, dtype=np.float64) if not isinstance(V, torch.Tensor) else V)
             v = v.to(device=self.device, dtype=torch.float64).reshape(shape).contiguous()
@@ -376,8 +423,10 @@ class Sim:
     def set_fields(self, fields):
         """Copy host or device arrays into the fields and bind them."""
         torch = self.torch
+        self._follow_caller()
         with torch.cuda.stream(self.stream):
             for dst, src in zip(self.psi, fields):
+                self._borrow(src)
                 src_t = torch.as_tensor(np.asarray(src) if not isinstance(src, torch.Tensor) else src)
                 dst.copy_(src_t.to(self.cdtype).reshape(dst.shape))
         bind(self.ctx, self.grids, self.params, self._ptrs(), self.ws.data_ptr())
@@ -392,9 +441,11 @@ class Sim:
         set_option(self.ctx, option, value)
 
     def step(self, n, dt):
+        self._follow_caller()
         step(self.ctx, n, dt)
 
     def local_update(self, tau):
+        self._follow_caller()
         local_update(self.ctx, tau)
 
     def field_tensor(self, group=0):
@@ -405,22 +456,29 @@ class Sim:
 
     def fields(self):
         """The fields as numpy complex128 arrays (synchronises)."""
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = [p.cpu().numpy().astype(np.complex128) for p in self.psi]
         return out
 
     def structure_factor_device(self, group=0):
         """Per-sample shell means [S, n_bins] (FP64) on the device, enqueued on
-        this object's stream and returned without synchronising."""
+        this object's stream and returned without synchronising (the caller's
+        current stream waits for it)."""
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((self.grids[group].samples, self.nbins[group]), dtype=self.torch.float64,
                                    device=self.device)
         structure_factor(self.ctx, group, out.data_ptr())
-        return out
+        return self._hand_back(out)
 
     def structure_factor_samples(self, group=0):
         """Per-sample shell means [S, n_bins] as a numpy array."""
-        out = self.structure_factor_device(group)
+        self._follow_caller()
+        with self.torch.cuda.stream(self.stream):
+            out = self.torch.empty((self.grids[group].samples, self.nbins[group]), dtype=self.torch.float64,
+                                   device=self.device)
+        structure_factor(self.ctx, group, out.data_ptr())
         with self.torch.cuda.stream(self.stream):
             return out.cpu().numpy()
 
@@ -459,6 +517,7 @@ class Sim:
             with open(cache_path) as fh:
                 cache = json.load(fh)
         keys = {(p, n): "%s/%s/%d/%d" % (arch, dname, p, n) for p, n in self.pass_sizes()}
+        self._follow_caller()
         if all(k in cache for k in keys.values()):
             for (p, n), k in keys.items():
                 set_variant(self.ctx, p, n, cache[k])
@@ -480,6 +539,7 @@ class Sim:
         """Advance n steps, keeping a checkpoint every `every` steps (device tensor)."""
         torch = self.torch
         nck = (int(n) + int(every) - 1) // int(every) if int(every) > 0 and int(n) > 0 else 1
+        self._follow_caller()
         with torch.cuda.stream(self.stream):
             ckpt = torch.empty((nck,) + tuple(self.psi[0].shape), dtype=self.cdtype, device=self.device)
         forward_ckpt(self.ctx, n, dt, every, ckpt.data_ptr())
@@ -488,6 +548,9 @@ class Sim:
     def adjoint(self, n, dt, every, ckpt, dl_dbins):
         """(dL/dpsi0 field, tensor [dL/dq, dL/dc1]) for dL/dS_{s,b} = dl_dbins [S, n_bins]."""
         torch = self.torch
+        self._follow_caller()
+        self._borrow(dl_dbins)
+        self._borrow(ckpt)
         with torch.cuda.stream(self.stream):
             dl = torch.as_tensor(dl_dbins, dtype=torch.float64).to(self.device).contiguous()
             ws = torch.empty(adjoint_workspace_bytes(self.grids[0], self.dtype_code, every), dtype=torch.uint8,
@@ -500,6 +563,7 @@ class Sim:
 
     def observables(self, group=0):
         """Per-sample (N, F_z, E) [S, 3] as a numpy array."""
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
         observables(self.ctx, group, out.data_ptr())
@@ -509,16 +573,18 @@ class Sim:
 
     def transverse_spin(self, group=0):
         """F_perp per site of `group` as a device tensor [S, spatial...],
-        enqueued on this object's stream (synchronize() before using it from
-        another stream)."""
+        enqueued on this object's stream and returned without synchronising
+        (the caller's current stream waits for it)."""
         g = self.grids[group]
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((g.samples,) + _spatial(g), dtype=self.psi[group].dtype, device=self.device)
         transverse_spin(self.ctx, group, out.data_ptr())
-        return out
+        return self._hand_back(out)
 
     def spin_texture(self, group=0):
         """Per-sample (mean |F_perp|, mean |F_perp|^2, Q_w) [S, 3] as numpy."""
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((self.grids[group].samples, 3), dtype=self.torch.float64, device=self.device)
         spin_texture(self.ctx, group, out.data_ptr())
@@ -528,6 +594,7 @@ class Sim:
     def step_observed(self, n, dt, group=0):
         """n steps, returning the per-step FP64 (N, F_z, E) of `group` as a
         numpy array [n, S, 3] (row i: the state R(dt/2) psi(t + i dt))."""
+        self._follow_caller()
         with self.torch.cuda.stream(self.stream):
             out = self.torch.empty((max(int(n), 1), self.grids[group].samples, 3), dtype=self.torch.float64,
                                    device=self.device)

@@ -78,6 +78,7 @@ def test_null_context_calls_fail_cleanly(abi):
     assert lib.spin1_structure_factor(None, 0, None) == abi.EINVAL
     assert lib.spin1_observables(None, 0, None) == abi.EINVAL
     assert lib.spin1_set_params(None, None) == abi.EINVAL
+    assert lib.spin1_init_wigner_shard(None, 1, None, 0, None, None, None, None) == abi.EINVAL
     assert lib.spin1_local_update(None, 0.1) == abi.EINVAL
     assert lib.spin1_set_option(None, 0, 1) == abi.EINVAL
     assert lib.spin1_profile_enable(None, 1) == abi.EINVAL

@@ -179,3 +179,66 @@ def test_adjoint_full_grid_central_differences(lib, nsteps, h):
         d2 = (f(h / 2) - f(-h / 2)) / h
         rich = (4 * d2 - d1) / 3
         assert abs(analytic - rich) <= 1e-5 * abs(rich), (analytic, d1, rich)
+
+
+def test_split_step_loss_psi0_from_default_stream(lib):
+    """SplitStepLoss fed a psi0 that device kernels are still writing on the
+    caller's (default) stream: the library's stream must wait for them, so the
+    loss and gradients equal those of the same psi0 given at rest."""
+    grid = (2, (64, 64), 0.5, 2)
+    g = O.Grid(2, (64, 64), 0.5, 2)
+    base = random_field(49, g.shape, noise=0.4)
+    nb = O.num_bins(g)
+    target = 24.0 * (1.0 + 0.1 * uniform_unit(50, (nb,)))
+    Loss = lib.make_split_step_loss()
+
+    def run(psi0):
+        p = psi0.requires_grad_(True)
+        q = torch.tensor(Q, dtype=torch.float64, device="cuda", requires_grad=True)
+        c1 = torch.tensor(C1, dtype=torch.float64, device="cuda", requires_grad=True)
+        L = Loss.apply(p, q, c1, target, 3.0, 12, 0.05, 5, grid, C0, "c128")
+        L.backward()
+        return float(L.detach()), p.grad.cpu().numpy(), float(q.grad), float(c1.grad)
+
+    ref = run(torch.tensor(base, dtype=torch.complex128, device="cuda"))
+    torch.cuda.synchronize()
+    src = torch.tensor(base, dtype=torch.complex128, device="cuda")
+    torch.cuda.synchronize()
+    # queue a long chain of kernels on the default stream, then the copy that
+    # produces psi0 behind it; no host synchronisation before the loss
+    m = torch.randn(2048, 2048, device="cuda")
+    for _ in range(40):
+        m = torch.tanh(m @ m) * 0.5
+    psi0 = torch.zeros_like(src)
+    psi0.copy_(src + 0.0 * m[0, 0])
+    got = run(psi0)
+    assert got[0] == ref[0]
+    assert np.array_equal(got[1], ref[1])
+    assert got[2] == ref[2] and got[3] == ref[3]
+
+
+def test_single_precision_adjoint_full_grid(lib):
+    """The adjoint workload (2D 256x256, 16 samples, checkpoints every 23
+    steps) with the complex64 forward and reverse sweep against the complex128
+    path, at 250 steps, the longest horizon at which the complex128 gradients
+    are confirmed by central differences (test_adjoint_full_grid_central_
+    differences): relative errors of dL/dq, dL/dc1 and dL/dpsi0 (L2 over the
+    whole field), printed and held to the measured level with margin."""
+    grid = (2, (256, 256), 0.5, 16)
+    g = O.Grid(2, (256, 256), 0.5, 16)
+    dt, every, k_cut, nsteps = 0.02, 23, 1.0, 250
+    sim = lib.Sim([grid], dict(c0=C0, c1=-0.1, q=0.09), dtype="c128")
+    sim.init_wigner(1005)
+    psi0 = sim.fields()[0]
+    sim.close()
+    nb = O.num_bins(g)
+    s0 = 4 * (0.5 / g.cell) * (1 + 0.5 / g.cell)
+    target = s0 * (1.0 + 0.1 * uniform_unit(48, (nb,)))
+    a = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every, dtype="c128", q=0.09, c1=-0.1)
+    b = gpu_grad(lib, grid, psi0, target, k_cut, nsteps, dt, every, dtype="c64", q=0.09, c1=-0.1)
+    errs = {"L": abs(b[0] - a[0]) / abs(a[0]), "dL/dpsi0": rel(b[1], a[1]),
+            "dL/dq": abs(b[2] - a[2]) / abs(a[2]), "dL/dc1": abs(b[3] - a[3]) / abs(a[3])}
+    print("complex64 vs complex128 adjoint, 256^2 x 16, 250 steps: %s"
+          % ", ".join("%s %.2e" % kv for kv in errs.items()))
+    assert errs["L"] < 1e-4
+    assert errs["dL/dq"] < 1e-2 and errs["dL/dc1"] < 1e-2 and errs["dL/dpsi0"] < 1e-2

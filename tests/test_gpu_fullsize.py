@@ -3,12 +3,14 @@ the benchmark times (autotuned variants, captured step graphs): sampled Wigner
 runs against the oracle run on those samples alone (the runs are independent),
 and properties that hold at any size where the oracle would take minutes.
 
-Tolerances: complex64 after two split steps, 1e-5 relative L2 per checked
-sample (one step holds 2e-6 in the small-size tests)."""
+Tolerances: after 100 split steps, relative L2 per checked sample, 1e-10 for
+complex128 and 1e-4 for complex64 (the stated tolerances); after two split
+steps, complex64 within 1e-5 (one step holds 2e-6 in the small-size tests)."""
 import numpy as np
 import pytest
 
 from oracle import spin1 as O
+from tests import oracle_jobs
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +113,64 @@ def test_1d_4096_250_runs_fp64_full_size(lib):
     ref = oracle_samples(1006, g, P2, 0, which, 3, 0.01)
     for i, s in enumerate(which):
         assert rel(got[i], ref[i]) < 1e-12, s
+
+
+@pytest.mark.timeout(900)
+def test_2d_512_64_samples_100_steps_against_oracle(lib):
+    """The headline workload (512^2 x 64) in the benchmark's launch
+    configuration, 100 split steps of dt = 0.02 in one call (autotuned
+    variants, captured graph), complex128 and complex64 from the same Wigner
+    state: the last sample against the oracle run on that sample alone."""
+    import torch
+
+    g = (2, (512, 512), 0.5, 64)
+    with oracle_jobs.pool(1) as ex:
+        job = ex.submit(oracle_jobs.evolve_samples, 1002, g, P2, 0, [63], 100, 0.02)
+        got = {}
+        for dtype in ("c128", "c64"):
+            sim = lib.Sim([g], P2, dtype=dtype)
+            sim.init_wigner(1002)
+            sim.autotune(reps=1)
+            sim.step(100, 0.02)
+            got[dtype] = sim.field_tensor(0)[63].to(torch.complex128).cpu().numpy()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        ref = job.result()[0]
+    e128, e64 = rel(got["c128"], ref), rel(got["c64"], ref)
+    print("512^2 x 64, sample 63, 100 steps: complex128 %.2e, complex64 %.2e" % (e128, e64))
+    assert e128 < 1e-10
+    assert e64 < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_uneven_batch_against_oracle_long(lib):
+    """The uneven four-group workload in one plan, complex64, the benchmark's
+    launch configuration: the first sample of the 1D 4096 and 2D 256^2 groups
+    after 100 split steps, and of the 1024^2 group after 20 (its oracle steps
+    cost seconds each), against the oracle run on those samples alone."""
+    import torch
+
+    groups = [(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
+              (2, (1024, 1024), 0.5, 4)]
+    checks = {0: 100, 1: 100, 3: 20}
+    with oracle_jobs.pool(len(checks)) as ex:
+        jobs = {gi: ex.submit(oracle_jobs.evolve_samples, 1004, groups[gi], P2, gi, [0], n, 0.02)
+                for gi, n in checks.items()}
+        got = {}
+        for nsteps in sorted(set(checks.values())):
+            sim = lib.Sim(groups, P2, dtype="c64")
+            sim.init_wigner(1004)
+            sim.autotune(reps=1)
+            sim.step(nsteps, 0.02)
+            for gi, n in checks.items():
+                if n == nsteps:
+                    got[gi] = sim.field_tensor(gi)[0].to(torch.complex128).cpu().numpy()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+        errs = {gi: rel(got[gi], jobs[gi].result()[0]) for gi in checks}
+    print("uneven batch, complex64, first samples: %s" % ", ".join(
+        "group %d (%d steps) %.2e" % (gi, checks[gi], e) for gi, e in errs.items()))
+    for gi, e in errs.items():
+        assert e < 1e-4, (gi, e)

@@ -2,12 +2,13 @@
 
 Tolerances (relative L2 over all samples, components and sites, from
 identical initial fields): complex128 <= 1e-10 after 100 steps; complex64
-<= 1e-4 after 100 steps, or 10x the single-precision floor of the dynamics
-where that floor is higher.  The floor is the oracle run in FP64 with its
-state rounded to complex64 after every step: no single-precision code can
-beat it, and chaotic configurations (the 3D one amplifies a 1e-8 change of
-the initial state ~7000-fold in 100 steps) put it above 1e-4.  Single steps
-and transforms are held tighter.
+<= 1e-4 after 100 steps, and within FLOOR_FACTOR of the single-precision
+floor of the dynamics.  The floor is the oracle run in FP64 with its state
+rounded to complex64 after every step: no single-precision code can beat it,
+and chaotic configurations (the 3D one amplifies a 1e-8 change of the
+initial state ~7000-fold in 100 steps) put it above 1e-4, so the 3D case
+misses 1e-4 (an expected failure).  Single steps and transforms are held
+tighter.
 """
 import numpy as np
 import pytest
@@ -191,20 +192,51 @@ def test_one_step_3d_non_cubic(lib):
 
 
 # ------------------------------------------------------------------ 100 steps
-@pytest.mark.parametrize("grid,p,dt", [
+HUNDRED = [
     ((1, (256,), 0.5, 4), P1, 0.01),         # the 1D L=256 FP64 configuration
     ((2, (64, 32), 0.5, 3), P1, 0.02),       # several tiles, ragged pencil count
     ((3, (16, 16, 16), 0.5, 2), P3, 0.02),
-])
+]
+# largest measured ratio of the complex64 error to the single-precision floor
+# of the dynamics (below), with margin: the kernels' own rounding may add a
+# few times the floor, not more
+FLOOR_FACTOR = 8.0
+_hundred_cache = {}
+
+
+def hundred_step_case(lib, grid, p, dt):
+    """(complex128 error, complex64 error, floor) after 100 steps against the oracle."""
+    key = (grid, dt)
+    if key not in _hundred_cache:
+        og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+        psi0 = O.init_wigner(1001, og, oparams(p))
+        ref = O.evolve(psi0, 100, dt, oparams(p), og)
+        got = run_gpu(lib, grid, p, "c128", seed=1001, nsteps=100, dt=dt).fields()[0]
+        # complex64 starts from the rounded FP64 initial state
+        got32 = run_gpu(lib, grid, p, "c64", seed=1001, nsteps=100, dt=dt).fields()[0]
+        floor = single_precision_floor(psi0, 100, dt, p, og, ref)
+        _hundred_cache[key] = (rel(got, ref), rel(got32, ref), floor)
+    return _hundred_cache[key]
+
+
+@pytest.mark.parametrize("grid,p,dt", HUNDRED)
 def test_hundred_steps(lib, grid, p, dt):
-    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
-    psi0 = O.init_wigner(1001, og, oparams(p))
-    ref = O.evolve(psi0, 100, dt, oparams(p), og)
-    got = run_gpu(lib, grid, p, "c128", seed=1001, nsteps=100, dt=dt).fields()[0]
-    assert rel(got, ref) < 1e-10
-    # complex64 starts from the rounded FP64 initial state
-    got32 = run_gpu(lib, grid, p, "c64", seed=1001, nsteps=100, dt=dt).fields()[0]
-    assert rel(got32, ref) < max(1e-4, 10.0 * single_precision_floor(psi0, 100, dt, p, og, ref))
+    e128, e64, floor = hundred_step_case(lib, grid, p, dt)
+    print("%dD %s: complex128 %.2e; complex64 %.2e = %.2f x the floor %.2e"
+          % (grid[0], grid[1], e128, e64, e64 / floor, floor))
+    assert e128 < 1e-10
+    assert e64 < FLOOR_FACTOR * floor
+
+
+@pytest.mark.parametrize("grid,p,dt", [
+    HUNDRED[0], HUNDRED[1],
+    pytest.param(*HUNDRED[2], marks=pytest.mark.xfail(
+        strict=True, reason="the 3D parameters amplify rounding ~7000-fold in 100 steps: the single-precision "
+                            "floor of the dynamics itself (5e-4) is above 1e-4, so complex64 misses the target")),
+])
+def test_hundred_steps_single_precision_target(lib, grid, p, dt):
+    """The stated complex64 tolerance, 1e-4 relative L2 after 100 steps."""
+    assert hundred_step_case(lib, grid, p, dt)[1] < 1e-4
 
 
 def single_precision_floor(psi0, nsteps, dt, p, og, ref):
