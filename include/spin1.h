@@ -172,6 +172,21 @@ SPIN1_API int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins
  * E the energy whose Wirtinger derivative is the right-hand side of Eq. (2). */
 SPIN1_API int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev);
 
+/* spin1_observables for callers that cannot allocate device memory around
+ * the call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and the same results, with the FP64
+ * partial sums kept in a static device array of the library (32 MiB, one copy
+ * per GPU, held from the load of the library until the process ends) instead
+ * of the bound workspace.  The call allocates nothing.  Limit: a group needs
+ * (S * rows * 4 + the strided-pass partials) doubles, rows = Ny * Nz, and
+ * must fit the 32 MiB (e.g. 2D 512^2 x 384, 3D 256^3 x 8 do); a larger group
+ * returns SPIN1_EUNSUPPORTED before anything is launched.  Every call on a
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (from
+ * several contexts or streams) race, so the caller orders them.
+ * SPIN1_EHIP if the array's device address could not be obtained when the
+ * context was created. */
+SPIN1_API int spin1_observables_noalloc(spin1_ctx* ctx, int32_t group, double* obs_dev);
+
 /* Transverse spin F_perp = F_x + i F_y = sqrt2 (psi_1^* psi_0 + psi_0^* psi_-1)
  * of group `group` at every site (Sec. 2.1 and Fig. 1: spin length |F_perp|
  * and Larmor phase phi_L = arg F_perp): fperp_dev is a device array

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,54 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Static scratch of spin1_observables_noalloc: partial sums in a device array
+// of the library itself, so that the call needs no workspace region and
+// allocates nothing.  Each device holds its own copy (from the load of the
+// code object until the process ends).  Host code uses the address that
+// hipGetSymbolAddress returns per device, never the array's name.
+// ---------------------------------------------------------------------------
+static constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Once per device, with that device current (spin1_create): the device
+// address of its copy of the scratch array.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) {
+    g_scratch_ptr[dev] = ptr;
+    g_scratch_err[dev] = hipSuccess;
+  } else {
+    g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+}
+
+// the scratch address of device dev, or null with *err set
+void* scratch_of(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_ptr[dev] ? hipSuccess : g_scratch_err[dev];
+  if (*err == hipSuccess && !g_scratch_ptr[dev]) *err = hipErrorNotInitialized;
+  return g_scratch_ptr[dev];
+}
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -756,6 +805,7 @@ int spin1_create(spin1_ctx** out, int32_t dtype, void* stream) {
   c->dbl = dtype == SPIN1_C128;
   c->stream = static_cast<hipStream_t>(stream);
   c->device = dev;
+  scratch_setup(dev);  // the no-allocation observables' scratch on this device
   *out = c;
   return SPIN1_OK;
 }
@@ -878,29 +928,60 @@ int spin1_structure_factor(spin1_ctx* ctx, int32_t group, double* bins_dev) {
   return SPIN1_OK;
 }
 
+// The observables of group G: MEASURE passes writing FP64 partials to
+// part_x ([S*rows][4]), part_y and part_z (one per strided-pass workgroup,
+// nblk[1] and nblk[2] of them), then the per-sample finish into obs.
+static int enqueue_observables(spin1_ctx* ctx, const GroupState& G, double* part_x, double* part_y, double* part_z,
+                               double* obs) {
+  XPassArgs xa = xargs(ctx, G);
+  xa.part = part_x;
+  Prof pr(ctx, SPIN1_K_OBSERVABLES);
+  hipError_t e = launch_xpass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[0], xa);
+  if (e != hipSuccess) return hip_fail(e, "energy x-pass");
+  for (int a = 1; a < G.geo.dim; ++a) {
+    SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
+    sa.part = a == 1 ? part_y : part_z;
+    e = launch_spass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[a], sa);
+    if (e != hipSuccess) return hip_fail(e, "energy strided pass");
+  }
+  e = launch_obs_finish(ctx->stream, G.geo.S, part_x, G.geo.rows, G.geo.dim > 1 ? part_y : nullptr,
+                        G.lay.nblk[1] / G.geo.S, G.geo.dim > 2 ? part_z : nullptr, G.lay.nblk[2] / G.geo.S,
+                        cell_of(G.geo), obs);
+  if (e != hipSuccess) return hip_fail(e, "observables finish");
+  return SPIN1_OK;
+}
+
 int spin1_observables(spin1_ctx* ctx, int32_t group, double* obs_dev) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
   if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
   if (!obs_dev) return fail(SPIN1_EINVAL, "obs_dev is NULL");
   const GroupState& G = ctx->groups[size_t(group)];
-  XPassArgs xa = xargs(ctx, G);
-  xa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[0]));
-  Prof pr(ctx, SPIN1_K_OBSERVABLES);
-  hipError_t e = launch_xpass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[0], xa);
-  if (e != hipSuccess) return hip_fail(e, "energy x-pass");
-  for (int a = 1; a < G.geo.dim; ++a) {
-    SPassArgs sa = sargs(ctx, G, a, G.psi, int64_t(3) * G.geo.S);
-    sa.part = reinterpret_cast<double*>(at(ctx, G.lay.part[a]));
-    e = launch_spass(ctx->stream, ctx->dbl, MODE_MEASURE, G.geo.n[a], sa);
-    if (e != hipSuccess) return hip_fail(e, "energy strided pass");
-  }
-  const double* py = G.geo.dim > 1 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[1])) : nullptr;
-  const double* pz = G.geo.dim > 2 ? reinterpret_cast<const double*>(at(ctx, G.lay.part[2])) : nullptr;
-  e = launch_obs_finish(ctx->stream, G.geo.S, reinterpret_cast<const double*>(at(ctx, G.lay.part[0])), G.geo.rows, py,
-                        G.lay.nblk[1] / G.geo.S, pz, G.lay.nblk[2] / G.geo.S, cell_of(G.geo), obs_dev);
-  if (e != hipSuccess) return hip_fail(e, "observables finish");
-  return SPIN1_OK;
+  auto part = [&](int a) { return reinterpret_cast<double*>(at(ctx, G.lay.part[a])); };
+  return enqueue_observables(ctx, G, part(0), part(1), part(2), obs_dev);
+}
+
+int spin1_observables_noalloc(spin1_ctx* ctx, int32_t group, double* obs_dev) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (group < 0 || size_t(group) >= ctx->groups.size()) return fail(SPIN1_EINVAL, "group %d out of range", group);
+  if (!obs_dev) return fail(SPIN1_EINVAL, "obs_dev is NULL");
+  const GroupState& G = ctx->groups[size_t(group)];
+  // the same partials as the workspace layout, packed into the static scratch
+  const size_t ox = 0;
+  const size_t oy = align_up(ox + size_t(G.geo.S) * size_t(G.geo.rows) * 4 * sizeof(double));
+  const size_t oz = align_up(oy + size_t(G.lay.nblk[1]) * sizeof(double));
+  const size_t end = align_up(oz + size_t(G.lay.nblk[2]) * sizeof(double));
+  if (end > kNoAllocScratchBytes)
+    return fail(SPIN1_EUNSUPPORTED,
+                "group %d needs %zu bytes of partial sums; the static scratch of spin1_observables_noalloc holds %zu "
+                "(use spin1_observables)",
+                group, end, kNoAllocScratchBytes);
+  hipError_t e = hipSuccess;
+  char* base = static_cast<char*>(scratch_of(ctx->device, &e));
+  if (!base) return hip_fail(e, "address of the static scratch");
+  return enqueue_observables(ctx, G, reinterpret_cast<double*>(base + ox), reinterpret_cast<double*>(base + oy),
+                             reinterpret_cast<double*>(base + oz), obs_dev);
 }
 
 int spin1_transverse_spin(spin1_ctx* ctx, int32_t group, void* fperp_dev) {

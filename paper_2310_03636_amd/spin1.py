@@ -25,7 +25,7 @@ FUNCTIONS = [
     "spin1_workspace_bytes", "spin1_num_bins", "spin1_bin_counts", "spin1_bind",
     "spin1_init_wigner", "spin1_init_wigner_shard", "spin1_set_params", "spin1_set_potential", "spin1_step", "spin1_sync_field",
     "spin1_structure_factor",
-    "spin1_observables", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
+    "spin1_observables", "spin1_observables_noalloc", "spin1_step_observed", "spin1_transverse_spin", "spin1_spin_texture",
     "spin1_local_update", "spin1_set_option", "spin1_profile_enable",
     "spin1_profile_read", "spin1_adjoint_workspace_bytes", "spin1_forward_ckpt", "spin1_adjoint",
     "spin1_num_variants", "spin1_autotune", "spin1_get_variant", "spin1_set_variant", "spin1_last_error",
@@ -89,6 +89,7 @@ def load():
         "spin1_sync_field": (ctypes.c_int, [vp]),
         "spin1_structure_factor": (ctypes.c_int, [vp, i32, vp]),
         "spin1_observables": (ctypes.c_int, [vp, i32, vp]),
+        "spin1_observables_noalloc": (ctypes.c_int, [vp, i32, vp]),
         "spin1_step_observed": (ctypes.c_int, [vp, i64, f64, i32, vp]),
         "spin1_transverse_spin": (ctypes.c_int, [vp, i32, vp]),
         "spin1_spin_texture": (ctypes.c_int, [vp, i32, vp]),
@@ -232,6 +233,10 @@ def structure_factor(ctx, group, bins_ptr):
 
 def observables(ctx, group, obs_ptr):
     _check(load().spin1_observables(ctx, int(group), ctypes.c_void_p(int(obs_ptr))))
+
+
+def observables_noalloc(ctx, group, obs_ptr):
+    _check(load().spin1_observables_noalloc(ctx, int(group), ctypes.c_void_p(int(obs_ptr))))
 
 
 def step_observed(ctx, n, dt, group, obs_ptr):
