@@ -214,13 +214,13 @@ OTHER_CONFIGS = {
     "1d_4096_s250_c128": dict(groups=[(1, (4096,), 0.5, 250)], dtype="c128", dt=0.01, steps=200,
                               params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1006),
     "3d_256_s8_c64": dict(groups=[(3, (256, 256, 256), 0.5, 8)], dtype="c64", dt=0.02, steps=20,
-                          params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003, log=True),
+                          params=dict(c0=1.0, c1=-0.05, q=0.025), seed=1003, log=True, roofline="3d256_s8"),
     # the paper's own Lie scheme (Eqs. (3)-(5) in its order) on the main workload
     "2d_512_s64_c64_paper_scheme": dict(groups=[(2, (512, 512), 0.5, 64)], dtype="c64", dt=0.02, steps=20,
                                         params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002, scheme=1),
     # six times the main batch (2.4 GB of field, beyond the 256 MB last-level cache)
     "2d_512_s384_c64": dict(groups=[(2, (512, 512), 0.5, 384)], dtype="c64", dt=0.02, steps=20,
-                            params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002),
+                            params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002, roofline="2d512_s384"),
     # the main workload in a harmonic trap V(x) (the V_m of Eq. (4)) rising to 4 at the box faces
     "2d_512_s64_c64_trap": dict(groups=[(2, (512, 512), 0.5, 64)], dtype="c64", dt=0.02, steps=20,
                                 params=dict(c0=1.0, c1=-0.1, q=0.09), seed=1002, trap=4.0),
@@ -263,6 +263,16 @@ def other_configs():
                      "norm_sample0": float(obs[0, 0])}
         if name == MAIN_2D_NAME:
             out[name]["spin_texture"] = spin_texture_timing(sim)
+        if c.get("roofline"):
+            # the step passes of the same call timed one by one (direct
+            # launches, HIP events on the library's stream)
+            spin1.profile_read(sim.ctx)
+            spin1.profile_enable(sim.ctx, True)
+            sim.step(c["steps"], c["dt"])
+            prof = spin1.profile_read(sim.ctx)
+            spin1.profile_enable(sim.ctx, False)
+            out[name]["whole_step"] = whole_step_entry(out[name]["value"], c["groups"], c["dtype"])
+            out[name]["rooflines"] = pass_rooflines(prof, c["groups"], c["dtype"], c["roofline"])
         if c.get("log"):
             # the same steps with the per-step FP64 (N, F_z, E) log of group 0
             e0.record(sim.stream)
@@ -342,41 +352,106 @@ def full_run():
     return out
 
 
-def oracle_baseline(budget_s=20.0):
-    """The FP64 oracle on the host: one sample of the 512 x 512 workload,
-    split steps until about budget_s seconds have passed."""
+def oracle_run(job):
+    """One oracle run on one host thread (a worker process): sample `which` of
+    a workload, Strang steps until `budget_s` seconds have passed or `max_steps`
+    are done.  Returns (site-steps, seconds, steps)."""
+    dim, n, dx, samples, params, dt, seed, which, budget_s, max_steps = job
     import numpy as np
     from oracle import spin1 as O
 
-    w = WORKLOAD
-    g = O.Grid(2, w["n"], w["dx"], 1)
-    p = O.Params(**w["params"])
-    psi = O.init_wigner(w["seed"], g, p)
+    g = O.Grid(dim, n, dx, samples)
+    p = O.Params(**params)
+    psi = O.init_wigner(seed, g, p, samples=which)
+    sub = O.Grid(dim, n, dx, len(which))
     t0 = time.perf_counter()
-    nsteps = 0
-    while True:
-        psi = O.strang_step(psi, w["dt"], p, g)
-        nsteps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
+    k = 0
+    while k < max_steps:
+        psi = O.strang_step(psi, dt, p, sub)
+        k += 1
+        if time.perf_counter() - t0 >= budget_s:
             break
+    el = time.perf_counter() - t0
     assert np.isfinite(psi).all()
-    return g.sites * nsteps / el, nsteps, el
+    return sub.sites * len(which) * k, el, k
 
 
-def profile_pass():
-    """Short run for hardware-counter passes: a few split steps of the 2D
-    workload, then a plain device copy of 402.65 MB (read and written once) as
-    the calibration kernel of known traffic."""
+def host_workers():
+    """Worker processes for the oracle baseline: the cores this process may
+    run on, at most 16 (the host share of one GPU on the benchmark machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def oracle_baseline(budget_s=12.0):
+    """The FP64 oracle as it stands, on the host cores, in worker processes of
+    one thread each (spawned, with the BLAS/OpenMP thread counts set to 1):
+    (a) the main workload, one 512 x 512 sample per worker, steps until
+    budget_s; the rate is the sum of the workers' own rates (their timed loops
+    overlap); (b) the same sample on one thread alone; (c) the 1D 256 x 4
+    double-precision workload in full (1000 steps) on one thread."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+
+    w = WORKLOAD
+    workers = host_workers()
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in saved:
+        os.environ[k] = "1"
+    try:
+        ctx = multiprocessing.get_context("spawn")
+        main_job = lambda s, budget: (w["dim"], w["n"], w["dx"], w["samples"], w["params"], w["dt"], w["seed"], [s],
+                                      budget, 10 ** 9)
+        with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+            res = list(ex.map(oracle_run, [main_job(s % w["samples"], budget_s) for s in range(workers)]))
+        with ProcessPoolExecutor(max_workers=1, mp_context=ctx) as ex:
+            one = ex.submit(oracle_run, main_job(0, budget_s)).result()
+            c1 = ex.submit(oracle_run, (1, (256,), 0.5, 4, dict(c0=1.0, c1=-0.1, q=0.09), 0.01, 1001,
+                                        [0, 1, 2, 3], 10 ** 9, 1000)).result()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    rate = sum(r[0] / r[1] for r in res)
+    return {"value": rate, "unit": "site-steps/s", "cores": workers, "kind": "oracle",
+            "sample": "FP64 numpy oracle on the 512x512 workload: %d worker processes of one thread, one Wigner "
+                      "sample each, %d-%d Strang steps in about %.0f s each; rate = sum of the workers' rates"
+                      % (workers, min(r[2] for r in res), max(r[2] for r in res), budget_s),
+            "single_thread": {"value": one[0] / one[1], "unit": "site-steps/s", "steps": one[2],
+                              "seconds": one[1]},
+            "config_1d_256_s4_c128_full": {"value": c1[0] / c1[1], "unit": "site-steps/s", "steps": c1[2],
+                                            "seconds": c1[1], "threads": 1}}
+
+
+PROFILE_WORKLOADS = {
+    "2d512_s64": ([(2, (512, 512), 0.5, 64)], dict(c0=1.0, c1=-0.1, q=0.09), 0.02),
+    "2d512_s384": ([(2, (512, 512), 0.5, 384)], dict(c0=1.0, c1=-0.1, q=0.09), 0.02),
+    "3d256_s8": ([(3, (256, 256, 256), 0.5, 8)], dict(c0=1.0, c1=-0.05, q=0.025), 0.02),
+    "uneven": ([(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
+                (2, (1024, 1024), 0.5, 4)], dict(c0=1.0, c1=-0.1, q=0.09), 0.02),
+    "1d4096_s250": ([(1, (4096,), 0.5, 250)], dict(c0=1.0, c1=-0.1, q=0.09), 0.01),
+}
+
+
+def profile_pass(workload="2d512_s64"):
+    """Short run for hardware-counter passes: a few split steps of a workload
+    (direct launches, variants chosen by the autotuner as in the timed run),
+    then a plain device copy of 402.65 MB (read and written once) as the
+    calibration kernel of known traffic."""
     import torch
     from paper_2310_03636_amd import spin1
 
-    w = WORKLOAD
-    sim = spin1.Sim([(w["dim"], w["n"], w["dx"], w["samples"])], w["params"], dtype="c64")
-    sim.init_wigner(w["seed"])
+    groups, params, dt = PROFILE_WORKLOADS[workload]
+    sim = spin1.Sim(groups, dict(params, n0=1.0, wigner_var=0.5), dtype="c128" if workload == "1d4096_s250" else "c64")
+    sim.init_wigner(1002)
     variants = sim.autotune(reps=2)  # the same choice as the timed run
     sim.set_option(spin1.OPT_GRAPHS, 0)
-    sim.step(3, w["dt"])
+    sim.step(3, dt)
     sim.synchronize()
     sim.close()
     print("profile pass variants: %s" % json.dumps(variants), flush=True)
@@ -388,6 +463,43 @@ def profile_pass():
     print("profile pass done: copy of %d bytes" % (n * 8), flush=True)
 
 
+def pass_bytes(groups, dtype):
+    """Algorithmic bytes of one step pass over every group: the 3-component
+    field read and written once."""
+    import math
+    cb = 16 if dtype == "c128" else 8
+    return 2 * 3 * cb * sum(g[3] * math.prod(g[1]) for g in groups)
+
+
+def whole_step_entry(value, groups, dtype):
+    """The whole split step against the HBM roofline: site-steps/s times the
+    pass-model bytes of a site-step (one field read + write per axis pass)."""
+    import math
+    cb = 16 if dtype == "c128" else 8
+    sites = sum(g[3] * math.prod(g[1]) for g in groups)
+    bytes_per_site_step = sum(g[3] * math.prod(g[1]) * g[0] for g in groups) * 2 * 3 * cb / sites
+    achieved = value * bytes_per_site_step / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "bytes_per_site_step": bytes_per_site_step}
+
+
+def pass_rooflines(prof, groups, dtype, workload):
+    """Roofline entry of every step pass kind of a one-group workload:
+    algorithmic bytes per launch over the live average launch time."""
+    out = {}
+    nbytes = pass_bytes(groups, dtype)
+    for kind in ("xpass", "ypass", "zpass"):
+        total, n = prof.get(kind, (0.0, 0))
+        if not n:
+            continue
+        avg = total / n
+        achieved = nbytes / (avg / 1e3) / 1e9
+        out[kind] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "avg_launch_ms": avg, "launches": n,
+                     "algorithmic_bytes_per_launch": nbytes, "traffic": measured_traffic(kind, workload)}
+    return out
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -397,11 +509,17 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_xpass_ypass_2d512_s64.md")
-    if not os.path.exists(path):
+TRAFFIC_FILES = {"2d512_s64": "traffic_xpass_ypass_2d512_s64.md",
+                 "2d512_s384": "traffic_xpass_ypass_2d512_s384.md",
+                 "3d256_s8": "traffic_xpass_ypass_zpass_3d256_s8.md"}
+
+
+def measured_traffic(kernel, workload="2d512_s64"):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary, or None when the kernel sources changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(workload, ""))
+    if not os.path.isfile(path):
         return None
     rec = {}
     for line in open(path):
@@ -450,14 +568,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--profile-pass", action="store_true",
-                    help="short run for rocprofv3 counter passes (no JSON line)")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--profile-pass", nargs="?", const="2d512_s64", default=None,
+                    choices=sorted(PROFILE_WORKLOADS),
+                    help="short run of a workload for rocprofv3 counter passes (no JSON line)")
     args = ap.parse_args()
     if args.profile_pass:
-        profile_pass()
+        profile_pass(args.profile_pass)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the Wigner samples are independent, so N GPUs would each run "
@@ -474,6 +593,7 @@ def main():
     sites = w["n"][0] * w["n"][1]
     per_step_site_steps = w["samples"] * sites * w["split_steps"]
     grid = (w["dim"], w["n"], w["samples"])
+    grid4 = (w["dim"], w["n"], w["dx"], w["samples"])
 
     # timed region with per-kernel HIP events (direct launches)
     sim, wall, ev_ms, prof = run_gpu("c64", args.steps, args.warmup, profile=True)
@@ -511,10 +631,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        rate, n_cpu, el = oracle_baseline(args.cpu_budget)
-        cpu = {"value": rate, "unit": "site-steps/s", "cores": 1, "kind": "oracle",
-               "sample": "FP64 numpy oracle, 1 sample of the 512x512 grid, %d Strang steps in %.1f s "
-                         "(numpy elementwise ops and batched 3x3 eigh run on one thread)" % (n_cpu, el)}
+        cpu = oracle_baseline(args.cpu_budget)
 
     line = {
         "metric": "site-steps/s, spin-1 split-step (FP32 vs FP64 at stated err); HBM GB/s",
@@ -533,13 +650,23 @@ def main():
                                "reductions, dt=0.02; step = 100 split steps + 1 structure-factor snapshot",
                    "grid": list(w["n"]), "samples": w["samples"], "split_steps_per_step": w["split_steps"],
                    "dt": w["dt"], "params": w["params"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": dom, "scope": "the dominant kernel alone (live launch times)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": measured_traffic(dom),
                      "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes,
                      "valu": valu_entry(dom, dom_avg_ms)},
+        # the whole split step of the timed region and of the graph replay
+        "roofline_whole_step": dict(whole_step_entry(value, [grid4], "c64"),
+                                    frac_graph_replay=whole_step_entry(value_graph, [grid4], "c64")["frac"]),
+        # working sets beyond the 256 MB last-level cache: every pass of the
+        # 2.4 GB 2D batch and of the 3 GiB 3D batch
+        "rooflines_cache_cold": {
+            "2d512_s384": {"whole_step": others["2d_512_s384_c64"]["whole_step"],
+                           "passes": others["2d_512_s384_c64"]["rooflines"]},
+            "3d256_s8": {"whole_step": others["3d_256_s8_c64"]["whole_step"],
+                         "passes": others["3d_256_s8_c64"]["rooflines"]}},
         "autotuned_variants": variants,
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
-        "hbm_algorithmic_GBps_whole_step": None,
         "graph_replay": {"value": value_graph, "unit": "site-steps/s", "ms_per_step": evg_ms / args.steps},
         "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
                  "ms_per_step": ev64 / args.fp64_steps},
@@ -553,8 +680,6 @@ def main():
         "wall_s": wall,
         "cpu_baseline": cpu,
     }
-    # whole-step algorithmic bandwidth: 2 passes x 48 B per site per split step
-    line["hbm_algorithmic_GBps_whole_step"] = value * 2 * 48 / 1e9
     print(json.dumps(line))
 
 

@@ -196,8 +196,10 @@ __device__ __forceinline__ void dft(Cx<Real>* v) {
 // indices t + e*N/R, and in the last stage the outputs land on those same
 // indices, so input and output stay in registers in natural order.
 //
-// Lds: store(i, v), load(i) on the pencil's row and sync() (a workgroup
-// barrier).  tw: table exp(-2 pi i m / N), m < N, in global memory.
+// Lds: slot(i) (the LDS element of index i), off(k) (the slot step of a
+// compile-time index step k), store_slot / load_slot and sync() (a workgroup
+// barrier, or a wavefront one where the pencil lies in one wavefront).
+// tw: table exp(-2 pi i m / N), m < N, in global memory.
 // ---------------------------------------------------------------------------
 template <int N, int R, int Ns>
 struct StageRadix {
@@ -276,15 +278,16 @@ __device__ __forceinline__ void fft_stages(Cx<Real>* v, int t, Lds& lds, const T
 #pragma unroll
         for (int r = 0; r < Rs; ++r) v[u + r * U] = w[r];
       } else {
-        const int base = (b / Ns) * Ns * Rs + j;
+        const int sb = lds.slot((b / Ns) * Ns * Rs + j);
 #pragma unroll
-        for (int r = 0; r < Rs; ++r) lds.store(base + r * Ns, w[r]);
+        for (int r = 0; r < Rs; ++r) lds.store_slot(sb + Lds::off(r * Ns), w[r]);
       }
     }
     if constexpr (!last) {
       lds.sync();
+      const int lb = lds.slot(t);
 #pragma unroll
-      for (int e = 0; e < R; ++e) v[e] = lds.load(t + e * T);
+      for (int e = 0; e < R; ++e) v[e] = lds.load_slot(lb + Lds::off(e * T));
       lds.sync();
       fft_stages<Real, N, R, Ns * Rs>(v, t, lds, tw);
     }
@@ -354,15 +357,24 @@ __device__ __forceinline__ void fft_halfphase_ifft(Cx<Real>* v, int t, Lds& lds,
 //   exp(-i theta M) = 1 - i s M + c M^2,  theta = c1 tau,
 //   s = sin(|F| theta)/|F| = theta sinc(x/2) cos(x/2),
 //   c = (cos(|F| theta) - 1)/|F|^2 = -theta^2/2 sinc(x/2)^2,  x = |F| theta,
-// and the c0 part is the scalar phase exp(-i c0 n tau).  With g = F_+/sqrt2:
+// and the c0 part is the scalar phase exp(-i c0 n tau).  Applied to the state
+// psi that defines F, M takes a closed form: with the singlet-pair amplitude
+// Theta = 2 psi_{+1} psi_{-1} - psi_0^2 and the time-reversed spinor
+// tpsi_m = (-1)^m conj(psi_{-m}),
+//   M psi = n psi + Theta tpsi,  M tpsi = -n tpsi - conj(Theta) psi,
+// hence M^2 psi = (n^2 - |Theta|^2) psi = |F|^2 psi (the spin-1 identity
+// |F|^2 + |Theta|^2 = n^2), and
+//   exp(-i theta M) psi = (cos x - i n s) psi - i s Theta tpsi.
+// The general form (apply_M below, with g = F_+/sqrt2:
 //   (Mv)_{+1} = Fz v_{+1} + g* v_0,  (Mv)_0 = g v_{+1} + g* v_{-1},
-//   (Mv)_{-1} = g v_0 - Fz v_{-1}.
+//   (Mv)_{-1} = g v_0 - Fz v_{-1})
+// serves the reverse mode and the paper's scheme.
 // ---------------------------------------------------------------------------
-// Series kernels on u = y^2 for |y| <= pi/4 (Taylor series, remainder below
-// 1e-10 relative): sinc(y) = sin(y)/y and cos(y).
+// Series kernels on u = y^2 for |y| <= pi/4 (Taylor series): sinc(y) =
+// sin(y)/y to u^4 (remainder below 2.2e-9 relative) and cos(y) to u^5
+// (remainder below 2.5e-8 absolute), both under the single-precision ulp.
 __device__ __forceinline__ float sinc_series(float u) {
-  float p = fmaf(u, 1.0f / 39916800.0f, -1.0f / 362880.0f);
-  p = fmaf(u, p, 1.0f / 5040.0f);
+  float p = fmaf(u, -1.0f / 362880.0f, 1.0f / 5040.0f);
   p = fmaf(u, p, -1.0f / 120.0f);
   p = fmaf(u, p, 1.0f / 6.0f);
   return fmaf(-u, p, 1.0f);
@@ -528,23 +540,34 @@ template <typename Real>
 __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, Real c1) {
   const Real d1 = norm2(psi[0]), d0 = norm2(psi[1]), dm = norm2(psi[2]);
   const Real n = d1 + d0 + dm;
-  const Cx<Real> g = cmulc(psi[0], psi[1]) + cmulc(psi[1], psi[2]);
-  const Real fz = d1 - dm;
-  const Real f2 = Real(2) * norm2(g) + fz * fz;
+  // Theta = 2 psi_{+1} psi_{-1} - psi_0^2
+  const Cx<Real> pp = psi[0] * psi[2];
+  const Cx<Real> th = {Real(2) * pp.re - (psi[1].re * psi[1].re - psi[1].im * psi[1].im),
+                       Real(2) * (pp.im - psi[1].re * psi[1].im)};
+  // |F|^2 = n^2 - |Theta|^2: its rounding (a few ulp of n^2) only enters
+  // through x^2 = |F|^2 theta^2, i.e. relative to the step as (n theta)^2
+  const Real f2 = fmax(n * n - norm2(th), Real(0));
   const Real theta = c1 * tau;
-  Real s, c, sp, cp;
-  rotation_coeffs(f2, theta, &s, &c);
+  // sinc(x/2) and cos(x/2) from u = (x/2)^2
+  const Real u = f2 * (Real(0.25) * theta * theta);
+  Real sc, ch;
+  sinc_cos_from_square(u, &sc, &ch);
+  const Real s = theta * (sc * ch);           // sin(x) / |F|
+  const Real cm1 = Real(-2) * (u * sc) * sc;  // cos(x) - 1 = -2 sin^2(x/2)
+  Real sp, cp;
   angle_sincos(n * (c0 * tau), &sp, &cp);
-  Cx<Real> phi[3], chi[3];
-  apply_M(psi, phi, g, fz);
-  apply_M(phi, chi, g, fz);
-  const Cx<Real> ph = {cp, -sp};
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    // psi - i s phi + c chi
-    const Cx<Real> u = {psi[m].re + s * phi[m].im + c * chi[m].re, psi[m].im - s * phi[m].re + c * chi[m].im};
-    psi[m] = ph * u;
-  }
+  // psi_m <- a psi_m + b (-1)^m conj(psi_{-m}),
+  // a = exp(-i c0 n tau) (1 + (cos x - 1) - i n s), b = exp(-i c0 n tau) (-i s Theta).
+  // The small part (cos x - 1 - i n s) is multiplied by the phase factor and
+  // added to it last: rounding cos x itself (1 less a few ulp) to single
+  // precision biased the norm by ~1e-9 per step.
+  const Real ns = n * s;
+  const Cx<Real> a = {cp + (cp * cm1 - sp * ns), -sp - (sp * cm1 + cp * ns)};
+  const Cx<Real> b = Cx<Real>{cp, -sp} * Cx<Real>{s * th.im, -s * th.re};
+  const Cx<Real> p1 = psi[0], p0 = psi[1], pm = psi[2];
+  psi[0] = a * p1 - b * conj(pm);
+  psi[1] = a * p0 + b * conj(p0);
+  psi[2] = a * pm - b * conj(p1);
 }
 
 // ---------------------------------------------------------------------------

@@ -42,7 +42,10 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
   using PE = std::conditional_t<PLAIN, Cx<Real>, TabEntry<Real>>;
   __shared__ PE ph[2 * N];
   const int t = threadIdx.x % T;
-  const int p = threadIdx.x / T;
+  // a pencil of a whole number of wavefronts has a wave-uniform index: held
+  // in a scalar register, it makes the pencil's addresses scalar bases
+  int p = threadIdx.x / T;
+  if constexpr (T % 64 == 0) p = __builtin_amdgcn_readfirstlane(p);
   RowLds<Real, N, T, (T <= 64)> L{lds + p * RowPad<N, T>::ROW};
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
@@ -85,7 +88,8 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
   int64_t g = blockIdx.x;
   if (g >= groups) return;
   for (; g < groups; g += gridDim.x) {
-    const int64_t pid = (a.reverse ? groups - 1 - g : g) * P + p;
+    int64_t pid = (a.reverse ? groups - 1 - g : g) * P + p;
+    if constexpr (T % 64 == 0) pid = wave_uniform(pid);
     const bool active = pid < npen;
     C v[3][R];
     if (active) {

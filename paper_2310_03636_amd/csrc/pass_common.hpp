@@ -78,6 +78,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A value the caller knows to be the same in every lane of the wavefront,
+// moved to scalar registers (the compiler cannot always prove it uniform).
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // WAVE: every pencil lies inside one wavefront (N/R <= 64), so its exchanges
 // synchronise only that wavefront; otherwise the whole workgroup.
 template <typename Real, int N, int T, bool WAVE>
@@ -85,6 +93,15 @@ struct RowLds {
   Cx<Real>* row;
   __device__ __forceinline__ void store(int i, Cx<Real> v) { row[RowPad<N, T>::at(i)] = v; }
   __device__ __forceinline__ Cx<Real> load(int i) const { return row[RowPad<N, T>::at(i)]; }
+  // Slot of index i, and the slot step of a compile-time index step k: in the
+  // exchanges of the FFT stages (index base + k with k a multiple of the
+  // stage's sub-transform size, or t + e N/R) the low four bits of base and k
+  // never carry, so slot(base + k) = slot(base) + off(k), and one per-lane
+  // slot per stage serves every element through immediate offsets.
+  __device__ static __forceinline__ int slot(int i) { return RowPad<N, T>::at(i); }
+  __device__ static constexpr int off(int k) { return k + (k >> 4); }
+  __device__ __forceinline__ void store_slot(int s, Cx<Real> v) { row[s] = v; }
+  __device__ __forceinline__ Cx<Real> load_slot(int s) const { return row[s]; }
   __device__ __forceinline__ void sync() {
     if constexpr (WAVE)
       wave_sync();
@@ -101,6 +118,10 @@ struct ColLds {
   Cx<Real>* col;
   __device__ __forceinline__ void store(int i, Cx<Real> v) { col[i * PITCH] = v; }
   __device__ __forceinline__ Cx<Real> load(int i) const { return col[i * PITCH]; }
+  __device__ static __forceinline__ int slot(int i) { return i * PITCH; }
+  __device__ static constexpr int off(int k) { return k * PITCH; }
+  __device__ __forceinline__ void store_slot(int s, Cx<Real> v) { col[s] = v; }
+  __device__ __forceinline__ Cx<Real> load_slot(int s) const { return col[s]; }
   __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
