@@ -265,8 +265,7 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  * SPIN1_OPT_STEPS_PER_LAUNCH_1D: 1D groups run up to this many consecutive
  *   split steps in one launch, each sample held on chip between steps
  *   (range 1..1024); 1 = one x-pass launch per step, as for 2D/3D groups;
- *   0 (default) = automatic: 64 for Nx <= 2048, 1 at 4096 (where a sample no
- *   longer fits one workgroup's LDS and registers).  The result is the same
+ *   0 (default) = automatic: 64 at every length.  The result is the same
  *   map either way (same arithmetic, different kernel).
  * SPIN1_OPT_GROUPED_X: 1 (default) = when two or more bound groups are
  *   stepped one x-pass launch per step and have Nx in 16..1024 (FP32) or

@@ -483,14 +483,15 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
 int steps_per_launch(const spin1_ctx* ctx, const GroupState& G) {
   if (G.geo.dim != 1 || G.pot) return 1;  // the multi-step kernels take no trap potential
   if (ctx->steps_per_launch_1d > 0) return ctx->steps_per_launch_1d;
-  return G.geo.n[0] <= 2048 ? 64 : 1;
+  return 64;
 }
 
 bool multi_1d(const spin1_ctx* ctx, const GroupState& G) { return steps_per_launch(ctx, G) > 1; }
 
 // The component-group form of the 1D multi-step kernel unless chosen
 // otherwise (it was faster at every measured size and sample count; where its
-// LDS does not fit, Nx = 4096, the launcher takes the pencil form).
+// LDS does not fit, Nx = 4096, the launcher takes the pencil form, which holds
+// a sample in the registers of 512 threads).
 bool split_1d(const spin1_ctx* ctx, const GroupState&) { return ctx->kernel_1d != 1; }
 
 int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double dt) {

@@ -448,23 +448,31 @@ __device__ __forceinline__ void sinc_cos_from_square(float u, float* sc, float* 
 
 // Double precision: the same forms with series to u^8 (remainder below 1e-17
 // relative for |y| <= pi/4) and the library sincos, out of line, beyond.
+// A double constant cannot be an immediate operand of a VALU instruction, and
+// the compiler keeps such constants in vector registers (one pair each, live
+// across the kernel's loops); passed through a scalar register pair at the
+// point of use they cost a scalar move instead.
+__device__ __forceinline__ double sreg(double c) {
+  asm volatile("" : "+s"(c));
+  return c;
+}
 __device__ __forceinline__ double sinc_series(double u) {
-  double p = fma(u, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);
-  p = fma(u, p, 1.0 / 6227020800.0);
-  p = fma(u, p, -1.0 / 39916800.0);
-  p = fma(u, p, 1.0 / 362880.0);
-  p = fma(u, p, -1.0 / 5040.0);
-  p = fma(u, p, 1.0 / 120.0);
-  p = fma(u, p, -1.0 / 6.0);
+  double p = fma(u, sreg(1.0 / 355687428096000.0), sreg(-1.0 / 1307674368000.0));
+  p = fma(u, p, sreg(1.0 / 6227020800.0));
+  p = fma(u, p, sreg(-1.0 / 39916800.0));
+  p = fma(u, p, sreg(1.0 / 362880.0));
+  p = fma(u, p, sreg(-1.0 / 5040.0));
+  p = fma(u, p, sreg(1.0 / 120.0));
+  p = fma(u, p, sreg(-1.0 / 6.0));
   return fma(u, p, 1.0);
 }
 __device__ __forceinline__ double cos_series(double u) {
-  double q = fma(u, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);
-  q = fma(u, q, 1.0 / 479001600.0);
-  q = fma(u, q, -1.0 / 3628800.0);
-  q = fma(u, q, 1.0 / 40320.0);
-  q = fma(u, q, -1.0 / 720.0);
-  q = fma(u, q, 1.0 / 24.0);
+  double q = fma(u, sreg(1.0 / 20922789888000.0), sreg(-1.0 / 87178291200.0));
+  q = fma(u, q, sreg(1.0 / 479001600.0));
+  q = fma(u, q, sreg(-1.0 / 3628800.0));
+  q = fma(u, q, sreg(1.0 / 40320.0));
+  q = fma(u, q, sreg(-1.0 / 720.0));
+  q = fma(u, q, sreg(1.0 / 24.0));
   q = fma(u, q, -0.5);
   return fma(u, q, 1.0);
 }

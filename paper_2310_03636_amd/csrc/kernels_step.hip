@@ -184,41 +184,67 @@ k_xpass_grouped(XGroupArgs a) {
 // can keep it in registers for K consecutive split steps with no HBM traffic
 // in between: load, K x [R(tau) -> FFT -> phase -> inverse FFT], optional
 // closing R(dt/2), store.  One pencil per workgroup (the sample count is the
-// parallelism); tables in LDS: twiddles (half table for N = 4096) and the
-// kinetic phase for k <= N/2 (it is even in k), the Zeeman factor
-// exp(-i q dt) applied separately to m = +-1.
+// parallelism), radix 8, N/8 threads each holding the same eight sites of the
+// three components, so the local update needs no exchange.  LDS holds one
+// exchange row (the three transforms of a step take turns on it) and the
+// stage-ordered twiddles; the kinetic phase of the thread's own wavenumbers
+// (even in k) is loaded once into registers, and the Zeeman factor
+// exp(-i q dt) of m = +-1 is a uniform value.  At N = 4096 in double precision
+// the row and the twiddles take 135 KB of LDS.  The twiddles are re-read from
+// LDS in every step: kept in registers across steps (the compiler would hoist
+// them out of the step loop) they would need 84 more registers per thread in
+// double precision and spill.
 // --------------------------------------------------------------------------
 template <int N, typename Real>
 struct MultiCfg {
-  // radix 8 at every length: at Nx = 4096 it keeps 3 x 8 values per thread
-  // (512 threads), where radix 16 needs more registers than a thread has
   static constexpr int R = N <= 8 ? N : 8;
   static constexpr int T = N / R;
-  static constexpr bool HALF_TW = N >= 4096;
-  static constexpr int TW_N = HALF_TW ? N / 2 + 1 : N;
+  using TW = StagedTwiddles<Real, N, R>;
+  static constexpr bool fits() {
+    return RowPad<N, T>::ROW * int(sizeof(Cx<Real>)) + (TW::SIZE > 0 ? TW::SIZE : 1) * int(sizeof(TabEntry<Real>)) <=
+           160 * 1024;
+  }
 };
 
-template <typename Real, int N>
+// Forward FFT, multiply by the per-element factors ph[e] (and the uniform zq
+// when given), inverse FFT through conj(FFT(conj(.))).
+template <typename Real, int N, int R, class Lds, class TW>
+__device__ __forceinline__ void fft_regphase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
+                                                  const TabEntry<Real> (&ph)[R], const TabEntry<Real>* zq) {
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    Cx<Real> x = mul_tab(v[e], ph[e]);
+    if (zq) x = mul_tab(x, *zq);
+    v[e] = conj(x);
+  }
+  fft_pencil<Real, N, R>(v, t, lds, tw);
+#pragma unroll
+  for (int e = 0; e < R; ++e) v[e] = conj(v[e]);
+}
+
+template <typename Real, int N, bool ENABLED = MultiCfg<N, Real>::fits()>
 __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs a, int K, double dt, int open_half,
                                                                        int close_half) {
+ if constexpr (ENABLED) {
   using C = Cx<Real>;
   using Cfg = MultiCfg<N, Real>;
+  using TW = typename Cfg::TW;
   constexpr int R = Cfg::R, T = Cfg::T;
   __shared__ C lds[RowPad<N, T>::ROW];
-  __shared__ TabEntry<Real> stw[Cfg::TW_N];
-  __shared__ TabEntry<Real> ph0[N / 2 + 1];
-  __shared__ TabEntry<Real> zq;
+  __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
   const int t = threadIdx.x;
+  TabEntry<Real> ph[R];
+  TabEntry<Real> zq;
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph) + N;  // m = 0 row
-    for (int i = t; i < Cfg::TW_N; i += T) stw[i] = gtw[i];
-    for (int i = t; i <= N / 2; i += T) ph0[i] = gph[i];
-    if (t == 0) {
-      double sn, cs;
-      sincos(a.q * dt, &sn, &cs);
-      store_tab(&zq, cs, -sn);
-    }
+    for (int i = t; i < TW::SIZE; i += T) stw[i] = gtw[TW::exponent(i)];
+#pragma unroll
+    for (int e = 0; e < R; ++e) ph[e] = gph[t + e * T];
+    double sn, cs;
+    sincos(a.q * dt, &sn, &cs);
+    store_tab(&zq, cs, -sn);
     __syncthreads();
   }
   RowLds<Real, N, T, (T <= 64)> L{lds};
@@ -237,27 +263,28 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
       v[0][e] = site[0];
       v[1][e] = site[1];
       v[2][e] = site[2];
+      // one site at a time: interleaving the eight sites' updates would need
+      // registers the double-precision form does not have at 512 threads
+      if constexpr (sizeof(Real) == 8) __builtin_amdgcn_sched_barrier(0);
     }
   };
   for (int k = 0; k < K; ++k) {
     local_all(Real((k == 0 && open_half) ? 0.5 * dt : dt));
-    if constexpr (Cfg::HALF_TW) {
-      const HalfTwiddles<Real, N> tw{stw};
-      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
-      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
-      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
-    } else {
-      const TabEntry<Real>* tw = stw;
-      fft_halfphase_ifft<Real, N, R>(v[0], t, L, tw, ph0, &zq);
-      fft_halfphase_ifft<Real, N, R>(v[1], t, L, tw, ph0, static_cast<const TabEntry<Real>*>(nullptr));
-      fft_halfphase_ifft<Real, N, R>(v[2], t, L, tw, ph0, &zq);
-    }
+    // an offset the compiler cannot see through keeps the twiddle reads in
+    // the step loop (see above)
+    int keep = 0;
+    asm volatile("" : "+v"(keep));
+    const TW tw{stw + keep};
+    fft_regphase_ifft<Real, N, R>(v[0], t, L, tw, ph, &zq);
+    fft_regphase_ifft<Real, N, R>(v[1], t, L, tw, ph, static_cast<const TabEntry<Real>*>(nullptr));
+    fft_regphase_ifft<Real, N, R>(v[2], t, L, tw, ph, &zq);
   }
   if (close_half) local_all(Real(0.5 * dt));
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
     for (int e = 0; e < R; ++e) psi[m * a.sites + e * T] = v[m][e];
+ }
 }
 
 // --------------------------------------------------------------------------
@@ -392,6 +419,8 @@ static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double 
   if (split && SplitCfg<N>::template fits<Real>())
     hipLaunchKernelGGL((k_x1d_split<Real, N>), dim3(unsigned(a.S)), dim3(SplitCfg<N>::THREADS), 0, st, a, K, dt,
                        int(open_half), int(close_half));
+  else if (!MultiCfg<N, Real>::fits())
+    return hipErrorInvalidValue;
   else
     hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
                        int(open_half), int(close_half));
