@@ -267,11 +267,12 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   (range 1..1024); 1 = one x-pass launch per step, as for 2D/3D groups;
  *   0 (default) = automatic: 64 at every length.  The result is the same
  *   map either way (same arithmetic, different kernel).
- * SPIN1_OPT_GROUPED_X: 1 (default) = when two or more bound groups are
- *   stepped one x-pass launch per step and have Nx in 16..1024 (FP32) or
- *   16..512 (FP64), their x-passes run as one persistent launch per step
- *   (radix 8, groups back to back in one work list); 0 = one x-pass launch
- *   per group.  Same arithmetic either way.
+ * SPIN1_OPT_GROUPED_X: 1 = when two or more bound groups are stepped one
+ *   x-pass launch per step and have Nx in 16..1024 (FP32) or 16..512 (FP64),
+ *   their x-passes run as one persistent launch per step (radix 8, groups back
+ *   to back in one work list); 0 (default) = one x-pass launch per group, each
+ *   group's passes in a sequence of its own (see SPIN1_OPT_CONCURRENT_GROUPS).
+ *   Same arithmetic either way.
  * SPIN1_OPT_SCHEME: SPIN1_SCHEME_STRANG (default), the symmetric split with
  *   the exact local flow described at spin1_step; or SPIN1_SCHEME_PAPER, the
  *   paper's own scheme in its order (Sec. 2.2): per step the kinetic phase of
@@ -295,12 +296,14 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   SPIN1_TWIDDLES_COMPENSATED: hi+lo float pairs, so the constants carry no
  *   rounding of their own.  The radix constants of the in-register
  *   butterflies and the other passes use the compensated form either way.
- * SPIN1_OPT_CONCURRENT_GROUPS: 1 (default) = when a grouped x-pass runs,
- *   spin1_step issues the steps of the remaining groups on a second stream
- *   of the library's (default priority, created on first use), forked from
- *   the caller's stream at the start of the call and joined back into it at
- *   the end, so that they overlap; 0 = everything on the caller's stream.
- *   Not used while profiling or on the NULL stream.  Same results either way.
+ * SPIN1_OPT_CONCURRENT_GROUPS: 1 (default) = the independent step sequences
+ *   of a call (each group outside a grouped x-pass, and the grouped set) run
+ *   on the caller's stream and up to three streams of the library's (default
+ *   priority, created on first use), forked from the caller's stream at the
+ *   start of the call and joined back into it at the end, so that the passes
+ *   of different groups overlap (round robin beyond four sequences); 0 =
+ *   everything on the caller's stream, one sequence after the other.  Not used
+ *   while profiling or on the NULL stream.  Same results either way.
  * SPIN1_OPT_1D_KERNEL: the kernel of the multi-step 1D launches: 0 (default)
  *   and 2 = three thread groups per sample, one per component, regrouped
  *   through LDS for the local update (shorter step latency; Nx <= 2048, the

@@ -266,15 +266,17 @@ struct spin1_ctx {
   bool use_graphs = true;
   int64_t graph_max_steps = 1024;
   int steps_per_launch_1d = 0;  // 0: automatic (see spin1.h)
-  bool grouped_x = true;
+  bool grouped_x = false;
   int kernel_1d = 0;  // 0 automatic, 1 one thread group per sample, 2 component groups
   int scheme = SPIN1_SCHEME_STRANG;
   bool dithered_tables = true;  // FP32 streaming passes: dithered float tables
-  // groups outside the grouped x-pass run on a second stream of default
-  // priority, forked from and joined back into the caller's stream per call
+  // groups outside the grouped x-pass run on streams of their own (default
+  // priority), forked from and joined back into the caller's stream per call
   bool concurrent = true;
-  hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  static constexpr int kSideStreams = 3;  // with the caller's: four hardware queues
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t join_ev[kSideStreams] = {};
+  hipEvent_t fork_ev = nullptr;
   uint64_t version = 0;  // bumped whenever a captured graph could go stale
   uint64_t use_clock = 0;
   std::vector<GraphEntry> graphs;
@@ -288,8 +290,10 @@ struct spin1_ctx {
     drop_graphs();
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
-    if (join_ev) (void)hipEventDestroy(join_ev);
-    if (side) (void)hipStreamDestroy(side);
+    for (int i = 0; i < kSideStreams; ++i) {
+      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+      if (side[i]) (void)hipStreamDestroy(side[i]);
+    }
   }
 };
 
@@ -587,85 +591,105 @@ int enqueue_steps_paper(spin1_ctx* ctx, int64_t n, double dt) {
   return SPIN1_OK;
 }
 
-int ensure_side_stream(spin1_ctx* ctx) {
-  if (ctx->side) return SPIN1_OK;
-  hipStream_t s = nullptr;
-  hipEvent_t f = nullptr, j = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&j, hipEventDisableTiming);
-  if (e != hipSuccess) {  // all or nothing
-    if (j) (void)hipEventDestroy(j);
-    if (f) (void)hipEventDestroy(f);
-    if (s) (void)hipStreamDestroy(s);
-    return hip_fail(e, "second stream");
+// The side streams and events, created on first use, all or nothing.
+int ensure_side_streams(spin1_ctx* ctx) {
+  if (ctx->side[0]) return SPIN1_OK;
+  hipStream_t s[spin1_ctx::kSideStreams] = {};
+  hipEvent_t j[spin1_ctx::kSideStreams] = {};
+  hipEvent_t f = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+  for (int i = 0; i < spin1_ctx::kSideStreams && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&j[i], hipEventDisableTiming);
   }
-  ctx->side = s;
+  if (e != hipSuccess) {
+    for (int i = 0; i < spin1_ctx::kSideStreams; ++i) {
+      if (j[i]) (void)hipEventDestroy(j[i]);
+      if (s[i]) (void)hipStreamDestroy(s[i]);
+    }
+    if (f) (void)hipEventDestroy(f);
+    return hip_fail(e, "side streams");
+  }
+  for (int i = 0; i < spin1_ctx::kSideStreams; ++i) {
+    ctx->side[i] = s[i];
+    ctx->join_ev[i] = j[i];
+  }
   ctx->fork_ev = f;
-  ctx->join_ev = j;
   return SPIN1_OK;
 }
 
-// The steps of the groups outside the grouped x-pass: multi-step 1D chunks
-// and one launch sequence per step and group.
-int enqueue_other_groups(spin1_ctx* ctx, const std::vector<char>& in_set, int64_t n, double dt) {
-  for (auto& G : ctx->groups)
-    if (multi_1d(ctx, G)) {
-      const int rc = enqueue_group_multi(ctx, G, n, dt);
-      if (rc) return rc;
-    }
+// All n steps of one group outside the grouped x-pass: multi-step 1D chunks,
+// or one launch sequence per step.
+int enqueue_group_steps(spin1_ctx* ctx, const GroupState& G, int64_t n, double dt) {
+  if (multi_1d(ctx, G)) return enqueue_group_multi(ctx, G, n, dt);
   for (int64_t i = 0; i < n; ++i) {
+    const int rc = enqueue_group_step(ctx, G, G.psi, i == 0 ? 0.5 * dt : dt, i == n - 1 ? 0.5 * dt : 0.0, nullptr, i);
+    if (rc) return rc;
+  }
+  return SPIN1_OK;
+}
+
+// The steps of the grouped x-pass set: one grouped x-pass launch per step,
+// then the other passes of each group in the set.
+int enqueue_grouped_steps(spin1_ctx* ctx, const std::vector<size_t>& set, int64_t n, double dt) {
+  for (int64_t i = 0; i < n && !set.empty(); ++i) {
     const double pre = i == 0 ? 0.5 * dt : dt;
     const double close = i == n - 1 ? 0.5 * dt : 0.0;
-    for (size_t g = 0; g < ctx->groups.size(); ++g) {
-      const GroupState& G = ctx->groups[g];
-      if (multi_1d(ctx, G) || in_set[g]) continue;
-      const int rc = enqueue_group_step(ctx, G, G.psi, pre, close, nullptr, i);
-      if (rc) return rc;
-    }
+    int rc = enqueue_grouped_x(ctx, set, pre, close, i);
+    for (size_t g : set)
+      if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close, i);
+    if (rc) return rc;
   }
   return SPIN1_OK;
 }
 
+// The independent sequences of a call: the grouped x-pass set (if any) and
+// every other group.  Sequences share no data, so with concurrent groups each
+// runs on a stream of its own (the caller's stream and up to three side
+// streams, forked from and joined back into the caller's stream; round robin
+// beyond four sequences), which lets the passes of small groups fill the GPU
+// together.
 int enqueue_steps(spin1_ctx* ctx, int64_t n, double dt) {
   if (ctx->scheme == SPIN1_SCHEME_PAPER) return enqueue_steps_paper(ctx, n, dt);
   const std::vector<size_t> set = grouped_x_set(ctx);
   std::vector<char> in_set(ctx->groups.size(), 0);
   for (size_t g : set) in_set[g] = 1;
-  const bool others = set.size() < ctx->groups.size();
-  // the other groups overlap the grouped ones on the second stream (not while
-  // profiling, whose events time the caller's stream)
-  const bool overlap = ctx->concurrent && !set.empty() && others && !ctx->prof && ctx->stream != nullptr;
-  int rc = SPIN1_OK;
-  if (overlap) {
-    if ((rc = ensure_side_stream(ctx))) return rc;
-    hipError_t e = hipEventRecord(ctx->fork_ev, ctx->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0);
-    if (e != hipSuccess) return hip_fail(e, "stream fork");
-    hipStream_t main = ctx->stream;
-    ctx->stream = ctx->side;
-    rc = enqueue_other_groups(ctx, in_set, n, dt);
-    ctx->stream = main;
-    e = hipEventRecord(ctx->join_ev, ctx->side);
-    if (rc || e != hipSuccess) {
-      // join even after a failed enqueue, so that a capture stays well formed
-      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
-      return rc ? rc : hip_fail(e, "stream join");
+  // sequence k: -1 = the grouped set, else a group index
+  std::vector<int> seqs;
+  if (!set.empty()) seqs.push_back(-1);
+  for (size_t g = 0; g < ctx->groups.size(); ++g)
+    if (!in_set[g]) seqs.push_back(int(g));
+  auto enqueue_seq = [&](int q) {
+    return q < 0 ? enqueue_grouped_steps(ctx, set, n, dt) : enqueue_group_steps(ctx, ctx->groups[size_t(q)], n, dt);
+  };
+  // side streams are not used while profiling (its events time the caller's
+  // stream) or on the NULL stream
+  const bool overlap = ctx->concurrent && seqs.size() > 1 && !ctx->prof && ctx->stream != nullptr;
+  if (!overlap) {
+    for (int q : seqs) {
+      const int rc = enqueue_seq(q);
+      if (rc) return rc;
     }
-  } else if (others) {
-    if ((rc = enqueue_other_groups(ctx, in_set, n, dt))) return rc;
+    return SPIN1_OK;
   }
-  for (int64_t i = 0; i < n && !set.empty(); ++i) {
-    const double pre = i == 0 ? 0.5 * dt : dt;
-    const double close = i == n - 1 ? 0.5 * dt : 0.0;
-    rc = enqueue_grouped_x(ctx, set, pre, close, i);
-    for (size_t g : set)
-      if (!rc) rc = enqueue_group_rest(ctx, ctx->groups[g], ctx->groups[g].psi, close, i);
-    if (rc) break;
+  int rc = ensure_side_streams(ctx);
+  if (rc) return rc;
+  const int nside = int(std::min<size_t>(seqs.size() - 1, spin1_ctx::kSideStreams));
+  hipError_t e = hipEventRecord(ctx->fork_ev, ctx->stream);
+  for (int i = 0; i < nside && e == hipSuccess; ++i) e = hipStreamWaitEvent(ctx->side[i], ctx->fork_ev, 0);
+  if (e != hipSuccess) return hip_fail(e, "stream fork");
+  hipStream_t main = ctx->stream;
+  for (size_t k = 0; k < seqs.size() && !rc; ++k) {
+    const int lane = int(k % size_t(nside + 1));  // 0: the caller's stream
+    ctx->stream = lane == 0 ? main : ctx->side[lane - 1];
+    rc = enqueue_seq(seqs[k]);
   }
-  if (overlap) {  // the main stream waits for the side stream's work, after its own
-    const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->join_ev, 0);
-    if (!rc && e != hipSuccess) return hip_fail(e, "stream join");
+  ctx->stream = main;
+  // join every side stream, also after a failed enqueue, so that a capture stays well formed
+  for (int i = 0; i < nside; ++i) {
+    hipError_t je = hipEventRecord(ctx->join_ev[i], ctx->side[i]);
+    if (je == hipSuccess) je = hipStreamWaitEvent(ctx->stream, ctx->join_ev[i], 0);
+    if (je != hipSuccess && !rc) rc = hip_fail(je, "stream join");
   }
   return rc;
 }

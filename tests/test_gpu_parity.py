@@ -410,12 +410,15 @@ def test_grouped_x_pass_matches_oracle(lib, dtype, tol):
         assert rel(out[1][gi], out[0][gi]) < tol / 10, gi
 
 
-def test_more_groups_than_one_grouped_launch_takes(lib):
-    """Nine eligible groups: eight share the grouped x-pass, the ninth runs its
-    own launches (on the second stream); all match the oracle."""
+@pytest.mark.parametrize("grouped", [1, 0])
+def test_more_groups_than_one_grouped_launch_takes(lib, grouped):
+    """Nine eligible groups.  Grouped: eight share the grouped x-pass, the
+    ninth runs its own launches on a side stream.  Not grouped: nine
+    sequences on four streams, round robin.  All match the oracle."""
     sizes = [(16, 16), (32, 16), (16, 32), (64, 16), (16, 64), (32, 32), (128, 16), (16, 128), (64, 32)]
     grids = [(2, n, 0.5, 1) for n in sizes]
     sim = lib.Sim(grids, P1, dtype="c128")
+    sim.set_option(lib.OPT_GROUPED_X, grouped)
     sim.init_wigner(25)
     sim.step(6, 0.02)
     f = sim.fields()
@@ -425,15 +428,19 @@ def test_more_groups_than_one_grouped_launch_takes(lib):
         assert rel(f[gi], ref) < 1e-12, gi
 
 
-def test_concurrent_groups_match_one_stream(lib):
-    """Groups outside the grouped x-pass on the second stream (forked and
-    joined inside each call, captured into the graph): bit-identical to one
-    stream, over replays with eager work in between."""
-    grids = [(1, (4096,), 0.5, 3), (2, (64, 32), 0.5, 2), (1, (512,), 0.5, 2), (2, (128, 16), 0.5, 2)]
+@pytest.mark.parametrize("grouped", [0, 1])
+def test_concurrent_groups_match_one_stream(lib, grouped):
+    """Independent group sequences on streams of their own (forked and joined
+    inside each call, captured into the graph; with the grouped x-pass, the
+    grouped set is one sequence): bit-identical to one stream, over replays
+    with eager work in between."""
+    grids = [(1, (4096,), 0.5, 3), (2, (64, 32), 0.5, 2), (1, (512,), 0.5, 2), (2, (128, 16), 0.5, 2),
+             (3, (16, 16, 16), 0.5, 1)]
     sims = []
     for conc in (1, 0):
         s = lib.Sim(grids, P1, dtype="c64")
         s.set_option(lib.OPT_CONCURRENT_GROUPS, conc)
+        s.set_option(lib.OPT_GROUPED_X, grouped)
         s.init_wigner(24)
         sims.append(s)
     for rep in range(3):
