@@ -199,9 +199,11 @@ template <int N, typename Real>
 struct MultiCfg {
   static constexpr int R = N <= 8 ? N : 8;
   static constexpr int T = N / R;
+  static constexpr int SH = sizeof(Real) == 8 ? 3 : 4;  // row padding: one element after every 2^SH
   using TW = StagedTwiddles<Real, N, R>;
   static constexpr bool fits() {
-    return RowPad<N, T>::ROW * int(sizeof(Cx<Real>)) + (TW::SIZE > 0 ? TW::SIZE : 1) * int(sizeof(TabEntry<Real>)) <=
+    return RowPad<N, T, SH>::ROW * int(sizeof(Cx<Real>)) +
+               (TW::SIZE > 0 ? TW::SIZE : 1) * int(sizeof(TabEntry<Real>)) <=
            160 * 1024;
   }
 };
@@ -230,8 +232,8 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
   using C = Cx<Real>;
   using Cfg = MultiCfg<N, Real>;
   using TW = typename Cfg::TW;
-  constexpr int R = Cfg::R, T = Cfg::T;
-  __shared__ C lds[RowPad<N, T>::ROW];
+  constexpr int R = Cfg::R, T = Cfg::T, SH = Cfg::SH;
+  __shared__ C lds[RowPad<N, T, SH>::ROW];
   __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
   const int t = threadIdx.x;
   TabEntry<Real> ph[R];
@@ -247,7 +249,7 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
     store_tab(&zq, cs, -sn);
     __syncthreads();
   }
-  RowLds<Real, N, T, (T <= 64)> L{lds};
+  RowLds<Real, N, T, (T <= 64), SH> L{lds};
   C* psi = static_cast<C*>(a.psi) + int64_t(blockIdx.x) * 3 * a.sites + t;
   C v[3][R];
 #pragma unroll

@@ -63,10 +63,11 @@ static_assert(kPlainTwiddles == kStepVariants, "the dithered-table variants foll
 // One pencil per row with one padding element after every 16 (measured best
 // on gfx950 for the radix-8 exchanges: it breaks up the power-of-two strides
 // of the early stages across LDS banks).
-template <int N, int T>
+// SH: one padding element after every 2^SH.
+template <int N, int T, int SH = 4>
 struct RowPad {
-  static constexpr int ROW = N + N / 16;
-  __device__ static __forceinline__ int at(int i) { return i + (i >> 4); }
+  static constexpr int ROW = N + (N >> SH);
+  __device__ static __forceinline__ int at(int i) { return i + (i >> SH); }
 };
 
 // LDS ordering among the lanes of one wavefront: LDS instructions of a wave
@@ -88,18 +89,18 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
 
 // WAVE: every pencil lies inside one wavefront (N/R <= 64), so its exchanges
 // synchronise only that wavefront; otherwise the whole workgroup.
-template <typename Real, int N, int T, bool WAVE>
+template <typename Real, int N, int T, bool WAVE, int SH = 4>
 struct RowLds {
   Cx<Real>* row;
-  __device__ __forceinline__ void store(int i, Cx<Real> v) { row[RowPad<N, T>::at(i)] = v; }
-  __device__ __forceinline__ Cx<Real> load(int i) const { return row[RowPad<N, T>::at(i)]; }
+  __device__ __forceinline__ void store(int i, Cx<Real> v) { row[RowPad<N, T, SH>::at(i)] = v; }
+  __device__ __forceinline__ Cx<Real> load(int i) const { return row[RowPad<N, T, SH>::at(i)]; }
   // Slot of index i, and the slot step of a compile-time index step k: in the
   // exchanges of the FFT stages (index base + k with k a multiple of the
   // stage's sub-transform size, or t + e N/R) the low four bits of base and k
   // never carry, so slot(base + k) = slot(base) + off(k), and one per-lane
   // slot per stage serves every element through immediate offsets.
-  __device__ static __forceinline__ int slot(int i) { return RowPad<N, T>::at(i); }
-  __device__ static constexpr int off(int k) { return k + (k >> 4); }
+  __device__ static __forceinline__ int slot(int i) { return RowPad<N, T, SH>::at(i); }
+  __device__ static constexpr int off(int k) { return k + (k >> SH); }
   __device__ __forceinline__ void store_slot(int s, Cx<Real> v) { row[s] = v; }
   __device__ __forceinline__ Cx<Real> load_slot(int s) const { return row[s]; }
   __device__ __forceinline__ void sync() {
