@@ -838,3 +838,26 @@ def test_uniform_polar_and_ferromagnet_on_gpu(lib, dtype, tol):
     out = sim.fields()[0]
     assert np.max(np.abs(out[:, 0] - np.sqrt(0.8) * ph)) < tol * 10
     assert np.max(np.abs(out[:, 1:])) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 2e-6)])
+def test_out_of_line_sincos_under_divergence(lib, dtype, tol):
+    """A sample with one site of huge density shares a wavefront with a normal
+    sample (1D, 256 points: two pencils per wavefront).  That site's local
+    update takes the out-of-line sine/cosine (the angle c0 n tau is 1e6)
+    while the other lanes do not; the samples sharing wavefronts with it must
+    still match the oracle step (values held in the lanes that sit out a call
+    must survive it)."""
+    grid = (1, (256,), 0.5, 4)
+    og = O.Grid(1, (256,), 0.5, 4)
+    psi0 = random_field(61, og.shape, noise=0.4)
+    psi0[1, 1, 100] = 1.0e4  # n = 1e8 at one site of sample 1
+    ref = O.strang_step(psi0, 0.01, oparams(P1), og)
+    sim = lib.Sim([grid], P1, dtype=dtype)
+    sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, 1)  # the streaming x-pass, two pencils per wavefront
+    sim.set_fields([psi0])
+    sim.step(1, 0.01)
+    got = sim.fields()[0]
+    for s in (0, 2, 3):
+        assert rel(got[s], ref[s]) < tol, s
+    assert np.all(np.isfinite(got))
