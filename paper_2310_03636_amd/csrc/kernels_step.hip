@@ -185,42 +185,135 @@ k_xpass_grouped(XGroupArgs a) {
 // in between: load, K x [R(tau) -> FFT -> phase -> inverse FFT], optional
 // closing R(dt/2), store.  One pencil per workgroup (the sample count is the
 // parallelism), radix 8, N/8 threads each holding the same eight sites of the
-// three components, so the local update needs no exchange.  LDS holds one
-// exchange row (the three transforms of a step take turns on it) and the
-// stage-ordered twiddles; the kinetic phase of the thread's own wavenumbers
-// (even in k) is loaded once into registers, and the Zeeman factor
-// exp(-i q dt) of m = +-1 is a uniform value.  At N = 4096 in double precision
-// the row and the twiddles take 135 KB of LDS.  The twiddles are re-read from
+// three components, so the local update needs no exchange.  The kinetic phase
+// of the thread's own wavenumbers (even in k) is loaded once into registers,
+// and the Zeeman factor exp(-i q dt) of m = +-1 is a uniform value.
+//
+// LDS holds the exchange rows and the twiddles.  Where N is a power of the
+// radix and two rows fit, the exchanges use the two rows in turn, which
+// halves the workgroup barriers (see fft_stages_2row).  In double precision
+// the twiddles are then held as one base value per butterfly and stage (see
+// BaseTwiddles), 9 KB at N = 4096 instead of 64 KB for every power, which is
+// what makes room for the second 72 KB row.  The twiddles are re-read from
 // LDS in every step: kept in registers across steps (the compiler would hoist
-// them out of the step loop) they would need 84 more registers per thread in
-// double precision and spill.
+// them out of the step loop) they would spill.
 // --------------------------------------------------------------------------
+
+// Double precision: the twiddles of the stage with sub-transform size Ns as
+// the one base value w^j per butterfly (w = exp(-2 pi i / (Ns R))), the stages
+// Ns = R, R^2, ..., N/R one after another from entry (Ns - R)/(R - 1).  The
+// powers w^(j r) are formed in registers by products of depth at most three
+// (a few units of FP64 rounding, against one for a table of every power).
+template <int N, int R>
+struct BaseTwiddles {
+  const Cx<double>* t;
+  static constexpr int SIZE = (N - R) / (R - 1);
+  // exponent m of entry i in exp(-2 pi i m / N) (table construction)
+  __device__ static __forceinline__ int exponent(int i) {
+    int ns = R;
+    while (i >= ns) {
+      i -= ns;
+      ns *= R;
+    }
+    return i * (N / (ns * R));
+  }
+};
+
+template <int R>
+__device__ __forceinline__ void twiddle_powers(Cx<double> (&p)[R], Cx<double> w) {
+  p[1] = w;
+#pragma unroll
+  for (int r = 2; r < R; ++r) p[r] = (r % 2 == 0) ? p[r / 2] * p[r / 2] : p[r / 2 + 1] * p[r / 2];
+}
+
+template <int N, int Ns, int R, typename Real>
+__device__ __forceinline__ void apply_twiddles(Cx<Real> (&w)[R], const StagedTwiddles<Real, N, R>& tw, int j) {
+#pragma unroll
+  for (int r = 1; r < R; ++r) w[r] = mul_tab(w[r], tw_at<N, Ns, R>(tw, j, r));
+}
+template <int N, int Ns, int R>
+__device__ __forceinline__ void apply_twiddles(Cx<double> (&w)[R], const BaseTwiddles<N, R>& tw, int j) {
+  Cx<double> p[R];
+  twiddle_powers<R>(p, tw.t[(Ns - R) / (R - 1) + j]);
+#pragma unroll
+  for (int r = 1; r < R; ++r) w[r] = w[r] * p[r];
+}
+
+// The stages of fft_stages for N a power of R (one butterfly per thread, the
+// same index maps), with two exchange rows ROW elements apart used in turn.
+// An exchange writes the row at offset buf, waits at a barrier and reads it
+// back; the next exchange writes the other row, which every thread finished
+// reading before that barrier, so the barrier after the reads is not needed.
+// buf (0 or ROW) carries the turn from one transform to the next.
+template <typename Real, int N, int R, int ROW, int Ns, class Lds, class TW>
+__device__ __forceinline__ void fft_stages_2row(Cx<Real>* v, int t, Lds& lds, int& buf, const TW& tw) {
+  if constexpr (Ns < N) {
+    constexpr int T = N / R;
+    static_assert(StageRadix<N, R, Ns>::value == R, "N must be a power of R");
+    const int j = t & (Ns - 1);
+    Cx<Real> w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[r] = v[r];
+    if constexpr (Ns > 1) apply_twiddles<N, Ns, R>(w, tw, j);
+    dft<Real, R>(w);
+    if constexpr (Ns * R == N) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = w[r];
+    } else {
+      const int sb = lds.slot((t / Ns) * Ns * R + j) + buf;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds.store_slot(sb + Lds::off(r * Ns), w[r]);
+      lds.sync();
+      const int lb = lds.slot(t) + buf;
+#pragma unroll
+      for (int e = 0; e < R; ++e) v[e] = lds.load_slot(lb + Lds::off(e * T));
+      buf = ROW - buf;
+      fft_stages_2row<Real, N, R, ROW, Ns * R>(v, t, lds, buf, tw);
+    }
+  }
+}
+
 template <int N, typename Real>
 struct MultiCfg {
   static constexpr int R = N <= 8 ? N : 8;
   static constexpr int T = N / R;
   static constexpr int SH = sizeof(Real) == 8 ? 3 : 4;  // row padding: one element after every 2^SH
-  using TW = StagedTwiddles<Real, N, R>;
-  static constexpr bool fits() {
-    return RowPad<N, T, SH>::ROW * int(sizeof(Cx<Real>)) +
-               (TW::SIZE > 0 ? TW::SIZE : 1) * int(sizeof(TabEntry<Real>)) <=
-           160 * 1024;
-  }
+  static constexpr int ROW = RowPad<N, T, SH>::ROW;
+  static constexpr bool POW = N == 8 || N == 64 || N == 512 || N == 4096;  // N a power of R
+  static constexpr bool BASE = sizeof(Real) == 8 && POW && N > R;
+  using TW = std::conditional_t<BASE, BaseTwiddles<N, R>, StagedTwiddles<Real, N, R>>;
+  using TWE = std::conditional_t<BASE, Cx<double>, TabEntry<Real>>;
+  static constexpr int TW_ENTRIES = TW::SIZE > 0 ? TW::SIZE : 1;
+  static constexpr int TW_BYTES = TW_ENTRIES * int(sizeof(TWE));
+  static constexpr int ROW_BYTES = ROW * int(sizeof(Cx<Real>));
+  static constexpr bool TWO_ROWS = POW && 2 * ROW_BYTES + TW_BYTES <= 160 * 1024;
+  static_assert(!BASE || TWO_ROWS, "the base-value twiddles serve the two-row form");
+  static constexpr int ROWS = TWO_ROWS ? 2 : 1;
+  static constexpr bool fits() { return ROWS * ROW_BYTES + TW_BYTES <= 160 * 1024; }
 };
 
 // Forward FFT, multiply by the per-element factors ph[e] (and the uniform zq
 // when given), inverse FFT through conj(FFT(conj(.))).
-template <typename Real, int N, int R, class Lds, class TW>
-__device__ __forceinline__ void fft_regphase_ifft(Cx<Real>* v, int t, Lds& lds, const TW& tw,
-                                                  const TabEntry<Real> (&ph)[R], const TabEntry<Real>* zq) {
-  fft_pencil<Real, N, R>(v, t, lds, tw);
+template <typename Real, int N, class Lds, class TW>
+__device__ __forceinline__ void fft_regphase_ifft(Cx<Real>* v, int t, Lds& lds, int& buf, const TW& tw,
+                                                  const TabEntry<Real> (&ph)[MultiCfg<N, Real>::R],
+                                                  const TabEntry<Real>* zq) {
+  using Cfg = MultiCfg<N, Real>;
+  constexpr int R = Cfg::R;
+  auto fft = [&]() {
+    if constexpr (Cfg::TWO_ROWS)
+      fft_stages_2row<Real, N, R, Cfg::ROW, 1>(v, t, lds, buf, tw);
+    else
+      fft_pencil<Real, N, R>(v, t, lds, tw);
+  };
+  fft();
 #pragma unroll
   for (int e = 0; e < R; ++e) {
     Cx<Real> x = mul_tab(v[e], ph[e]);
     if (zq) x = mul_tab(x, *zq);
     v[e] = conj(x);
   }
-  fft_pencil<Real, N, R>(v, t, lds, tw);
+  fft();
 #pragma unroll
   for (int e = 0; e < R; ++e) v[e] = conj(v[e]);
 }
@@ -232,24 +325,33 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
   using C = Cx<Real>;
   using Cfg = MultiCfg<N, Real>;
   using TW = typename Cfg::TW;
+  using TWE = typename Cfg::TWE;
   constexpr int R = Cfg::R, T = Cfg::T, SH = Cfg::SH;
-  __shared__ C lds[RowPad<N, T, SH>::ROW];
-  __shared__ TabEntry<Real> stw[TW::SIZE > 0 ? TW::SIZE : 1];
+  __shared__ C lds[Cfg::ROWS * Cfg::ROW];
+  __shared__ TWE stw[Cfg::TW_ENTRIES];
   const int t = threadIdx.x;
   TabEntry<Real> ph[R];
   TabEntry<Real> zq;
   {
     const TabEntry<Real>* gtw = static_cast<const TabEntry<Real>*>(a.tw);
     const TabEntry<Real>* gph = static_cast<const TabEntry<Real>*>(a.ph) + N;  // m = 0 row
-    for (int i = t; i < TW::SIZE; i += T) stw[i] = gtw[TW::exponent(i)];
+    for (int i = t; i < TW::SIZE; i += T) {
+      if constexpr (Cfg::BASE) {
+        const TabEntry<Real> w = gtw[TW::exponent(i)];
+        stw[i] = C{w.hr, w.hi};
+      } else {
+        stw[i] = gtw[TW::exponent(i)];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < R; ++e) ph[e] = gph[t + e * T];
     double sn, cs;
     sincos(a.q * dt, &sn, &cs);
-    store_tab(&zq, cs, -sn);
+    store_tab(&zq, wave_uniform(cs), -wave_uniform(sn));  // the same in every lane
     __syncthreads();
   }
   RowLds<Real, N, T, (T <= 64), SH> L{lds};
+  int buf = 0;
   C* psi = static_cast<C*>(a.psi) + int64_t(blockIdx.x) * 3 * a.sites + t;
   C v[3][R];
 #pragma unroll
@@ -274,12 +376,12 @@ __global__ __launch_bounds__((MultiCfg<N, Real>::T)) void k_x1d_multi(XPassArgs 
     local_all(Real((k == 0 && open_half) ? 0.5 * dt : dt));
     // an offset the compiler cannot see through keeps the twiddle reads in
     // the step loop (see above)
-    int keep = 0;
-    asm volatile("" : "+v"(keep));
+    int keep = 0, tk = t;
+    asm volatile("" : "+v"(keep), "+v"(tk));
     const TW tw{stw + keep};
-    fft_regphase_ifft<Real, N, R>(v[0], t, L, tw, ph, &zq);
-    fft_regphase_ifft<Real, N, R>(v[1], t, L, tw, ph, static_cast<const TabEntry<Real>*>(nullptr));
-    fft_regphase_ifft<Real, N, R>(v[2], t, L, tw, ph, &zq);
+    fft_regphase_ifft<Real, N>(v[0], tk, L, buf, tw, ph, &zq);
+    fft_regphase_ifft<Real, N>(v[1], tk, L, buf, tw, ph, static_cast<const TabEntry<Real>*>(nullptr));
+    fft_regphase_ifft<Real, N>(v[2], tk, L, buf, tw, ph, &zq);
   }
   if (close_half) local_all(Real(0.5 * dt));
 #pragma unroll

@@ -86,6 +86,9 @@ __device__ __forceinline__ int64_t wave_uniform(int64_t v) {
   const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
   return int64_t((uint64_t(hi) << 32) | lo);
 }
+__device__ __forceinline__ double wave_uniform(double v) {
+  return __builtin_bit_cast(double, wave_uniform(__builtin_bit_cast(int64_t, v)));
+}
 
 // WAVE: every pencil lies inside one wavefront (N/R <= 64), so its exchanges
 // synchronise only that wavefront; otherwise the whole workgroup.
