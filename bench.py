@@ -483,11 +483,41 @@ def whole_step_entry(value, groups, dtype):
             "frac": achieved / HBM_PEAK_GBPS, "bytes_per_site_step": bytes_per_site_step}
 
 
+def copy_reference(nbytes, reps=10):
+    """A plain device copy (torch's copy_) between two buffers of half of
+    `nbytes` each, so that one launch reads and writes `nbytes` in all: the
+    rate HBM reaches for a streaming kernel of this volume on this GPU, a
+    practical ceiling beside the published peak.  Timed with HIP events on a
+    stream of its own (default priority) after three untimed copies."""
+    import torch
+
+    n = nbytes // 2 // 8  # complex64 elements of each buffer
+    src = torch.ones(n, dtype=torch.complex64, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            dst.copy_(src)
+        e0.record(st)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(st)
+    st.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "device copy (torch copy_) of a buffer the size of the field", "bytes_per_launch": nbytes,
+            "avg_launch_ms": ms, "achieved": nbytes / (ms / 1e3) / 1e9, "unit": "GB/s", "launches": reps}
+
+
 def pass_rooflines(prof, groups, dtype, workload):
     """Roofline entry of every step pass kind of a one-group workload:
-    algorithmic bytes per launch over the live average launch time."""
+    algorithmic bytes per launch over the live average launch time, and the
+    same bytes moved by a plain device copy for comparison."""
     out = {}
     nbytes = pass_bytes(groups, dtype)
+    cref = copy_reference(nbytes)
     for kind in ("xpass", "ypass", "zpass"):
         total, n = prof.get(kind, (0.0, 0))
         if not n:
@@ -496,7 +526,9 @@ def pass_rooflines(prof, groups, dtype, workload):
         achieved = nbytes / (avg / 1e3) / 1e9
         out[kind] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "avg_launch_ms": avg, "launches": n,
-                     "algorithmic_bytes_per_launch": nbytes, "traffic": measured_traffic(kind, workload)}
+                     "algorithmic_bytes_per_launch": nbytes, "traffic": measured_traffic(kind, workload),
+                     "frac_of_copy": achieved / cref["achieved"]}
+    out["copy_reference"] = cref
     return out
 
 
@@ -616,6 +648,7 @@ def main():
     dom_avg_ms = dom_ms / dom_n
     dom_bytes = algorithmic_bytes(dom, grid, 8)
     achieved = dom_bytes / (dom_avg_ms / 1e3) / 1e9 if dom_bytes else None
+    cref = copy_reference(dom_bytes) if dom_bytes else None
 
     sim64, wall64, ev64, _ = run_gpu("c128", args.fp64_steps, 1, profile=False)
     value64 = per_step_site_steps * args.fp64_steps / (ev64 / 1e3)
@@ -654,7 +687,8 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": measured_traffic(dom),
                      "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes,
-                     "valu": valu_entry(dom, dom_avg_ms)},
+                     "valu": valu_entry(dom, dom_avg_ms), "copy_reference": cref,
+                     "frac_of_copy": achieved / cref["achieved"] if cref else None},
         # the whole split step of the timed region and of the graph replay
         "roofline_whole_step": dict(whole_step_entry(value, [grid4], "c64"),
                                     frac_graph_replay=whole_step_entry(value_graph, [grid4], "c64")["frac"]),
