@@ -231,7 +231,9 @@ OTHER_CONFIGS = {
 
 
 def other_configs():
-    """Site-steps/s of the other workloads (graph replay, autotuned passes)."""
+    """Site-steps/s of the other workloads (graph replay, autotuned passes):
+    three calls of `steps` split steps each, timed together after one call
+    that captures the graph."""
     import torch
     from paper_2310_03636_amd import spin1
 
@@ -251,14 +253,16 @@ def other_configs():
         sim.step(c["steps"], c["dt"])  # capture and warm up
         sim.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
         e0.record(sim.stream)
-        sim.step(c["steps"], c["dt"])
+        for _ in range(reps):
+            sim.step(c["steps"], c["dt"])
         e1.record(sim.stream)
         sim.synchronize()
-        ms = e0.elapsed_time(e1)
+        ms = e0.elapsed_time(e1) / reps
         sites = sum(g[3] * int(__import__("math").prod(g[1])) for g in c["groups"])
         obs = sim.observables(0)
-        out[name] = {"value": sites * c["steps"] / (ms / 1e3), "unit": "site-steps/s", "steps": c["steps"],
+        out[name] = {"value": sites * c["steps"] / (ms / 1e3), "unit": "site-steps/s", "steps": c["steps"], "calls": reps,
                      "ms_per_split_step": ms / c["steps"], "dtype": c["dtype"], "variants": tuned,
                      "norm_sample0": float(obs[0, 0])}
         if name == MAIN_2D_NAME:
@@ -272,7 +276,7 @@ def other_configs():
             prof = spin1.profile_read(sim.ctx)
             spin1.profile_enable(sim.ctx, False)
             out[name]["whole_step"] = whole_step_entry(out[name]["value"], c["groups"], c["dtype"])
-            out[name]["rooflines"] = pass_rooflines(prof, c["groups"], c["dtype"], c["roofline"])
+            out[name]["rooflines"] = pass_rooflines(prof, c["groups"], c["dtype"], c["roofline"], tuned)
         if c.get("log"):
             # the same steps with the per-step FP64 (N, F_z, E) log of group 0
             e0.record(sim.stream)
@@ -442,7 +446,9 @@ def profile_pass(workload="2d512_s64"):
     """Short run for hardware-counter passes: a few split steps of a workload
     (direct launches, variants chosen by the autotuner as in the timed run),
     then a plain device copy of 402.65 MB (read and written once) as the
-    calibration kernel of known traffic."""
+    calibration kernel of known traffic.  A small fill kernel before the
+    steps and the fill of the copy's source after them bracket the steps in
+    a kernel trace."""
     import torch
     from paper_2310_03636_amd import spin1
 
@@ -451,6 +457,8 @@ def profile_pass(workload="2d512_s64"):
     sim.init_wigner(1002)
     variants = sim.autotune(reps=2)  # the same choice as the timed run
     sim.set_option(spin1.OPT_GRAPHS, 0)
+    torch.zeros(16, device="cuda")  # a fill kernel that marks the start of the steps in a trace
+    torch.cuda.synchronize()
     sim.step(3, dt)
     sim.synchronize()
     sim.close()
@@ -511,7 +519,7 @@ def copy_reference(nbytes, reps=10):
             "avg_launch_ms": ms, "achieved": nbytes / (ms / 1e3) / 1e9, "unit": "GB/s", "launches": reps}
 
 
-def pass_rooflines(prof, groups, dtype, workload):
+def pass_rooflines(prof, groups, dtype, workload, variants=None):
     """Roofline entry of every step pass kind of a one-group workload:
     algorithmic bytes per launch over the live average launch time, and the
     same bytes moved by a plain device copy for comparison."""
@@ -526,7 +534,8 @@ def pass_rooflines(prof, groups, dtype, workload):
         achieved = nbytes / (avg / 1e3) / 1e9
         out[kind] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "avg_launch_ms": avg, "launches": n,
-                     "algorithmic_bytes_per_launch": nbytes, "traffic": measured_traffic(kind, workload),
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "traffic": measured_traffic(kind, workload, variant_of(kind, groups, variants, dtype)),
                      "frac_of_copy": achieved / cref["achieved"]}
     out["copy_reference"] = cref
     return out
@@ -546,19 +555,34 @@ TRAFFIC_FILES = {"2d512_s64": "traffic_xpass_ypass_2d512_s64.md",
                  "3d256_s8": "traffic_xpass_ypass_zpass_3d256_s8.md"}
 
 
-def measured_traffic(kernel, workload="2d512_s64"):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summary, or None when the kernel sources changed since the
-    counters were taken."""
-    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(workload, ""))
-    if not os.path.isfile(path):
+def variant_of(kind, groups, variants, dtype="c64"):
+    """The autotuned variant of a pass kind on the first group (None if unknown)."""
+    axis = {"xpass": 0, "ypass": 1, "zpass": 2}[kind]
+    g = groups[0]
+    if axis >= len(g[1]):
         return None
+    return (variants or {}).get("gfx950/%s/%d/%d" % (dtype, 0 if axis == 0 else 1, g[1][axis]))
+
+
+def summary_lines(path, tag):
+    """{(kind, variant): fields} of the machine-readable `tag:` lines of a
+    committed profile summary."""
     rec = {}
-    for line in open(path):
-        if line.startswith("traffic:"):
-            parts = dict(kv.split("=") for kv in line.split()[1:])
-            rec[parts["kind"]] = parts
-    r = rec.get(kernel)
+    if os.path.isfile(path):
+        for line in open(path):
+            if line.startswith(tag + ":"):
+                parts = dict(kv.split("=") for kv in line.split()[1:])
+                rec[(parts["kind"], int(parts.get("variant", -1)))] = parts
+    return rec
+
+
+def measured_traffic(kernel, workload="2d512_s64", variant=None):
+    """HBM bytes per launch of `kernel` (of the given autotuned variant) on
+    `workload` from the committed counter summary, or None when the summary
+    has no such line or the kernel sources changed since the counters were
+    taken."""
+    rec = summary_lines(os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(workload, "")), "traffic")
+    r = rec.get((kernel, variant if variant is not None else 0))
     if not r or r.get("source") != kernel_source_hash():
         return None
     return float(r["bytes"])
@@ -567,27 +591,21 @@ def measured_traffic(kernel, workload="2d512_s64"):
 VALU_PEAK = 256 * 4 * 2.4e9 / 4  # wave64 FP32 VALU instructions per second (non-packed)
 
 
-def measured_valu(kernel):
-    """VALU wavefront instructions per launch of `kernel` from the committed
-    counter summary, or None when the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", "valu_xpass_ypass_2d512_s64.md")
-    if not os.path.exists(path):
-        return None
-    rec = {}
-    for line in open(path):
-        if line.startswith("valu:"):
-            parts = dict(kv.split("=") for kv in line.split()[1:])
-            rec[parts["kind"]] = parts
-    r = rec.get(kernel)
+def measured_valu(kernel, variant=None):
+    """VALU wavefront instructions per launch of `kernel` (of the given
+    autotuned variant) from the committed counter summary, or None when the
+    summary has no such line or the kernel sources changed since."""
+    rec = summary_lines(os.path.join(ROOT, "profiles", "valu_xpass_ypass_2d512_s64.md"), "valu")
+    r = rec.get((kernel, variant if variant is not None else 0))
     if not r or r.get("source") != kernel_source_hash():
         return None
     return float(r["instr"])
 
 
-def valu_entry(kernel, avg_ms):
+def valu_entry(kernel, avg_ms, variant=None):
     """The issue side of the same launch: counted VALU instructions per launch
     over the live launch time, against the non-packed FP32 issue ceiling."""
-    instr = measured_valu(kernel)
+    instr = measured_valu(kernel, variant)
     if instr is None:
         return None
     achieved = instr / (avg_ms / 1e3)
@@ -627,18 +645,20 @@ def main():
     grid = (w["dim"], w["n"], w["samples"])
     grid4 = (w["dim"], w["n"], w["dx"], w["samples"])
 
-    # timed region with per-kernel HIP events (direct launches)
-    sim, wall, ev_ms, prof = run_gpu("c64", args.steps, args.warmup, profile=True)
-    value = per_step_site_steps * args.steps / (ev_ms / 1e3)
-    variants = sim.variants
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    # the same steps replayed from captured HIP graphs (no per-kernel events)
-    simg, wallg, evg_ms, _ = run_gpu("c64", args.steps, args.warmup, profile=False)
-    value_graph = per_step_site_steps * args.steps / (evg_ms / 1e3)
+    # the timed region as the library runs it by default: each call's launches
+    # replayed from a captured HIP graph
+    simg, wall, evg_ms, _ = run_gpu("c64", args.steps, args.warmup, profile=False)
+    value = per_step_site_steps * args.steps / (evg_ms / 1e3)
+    variants = simg.variants
     simg.close()
     del simg
+    torch.cuda.empty_cache()
+    # the same steps as direct launches, each kernel timed by its own begin and
+    # end (the library's profiling mode): the per-kernel times of the rooflines
+    sim, wall_direct, ev_ms, prof = run_gpu("c64", args.steps, args.warmup, profile=True)
+    value_direct = per_step_site_steps * args.steps / (ev_ms / 1e3)
+    sim.close()
+    del sim
     torch.cuda.empty_cache()
 
     # dominant kernel and its live average duration
@@ -673,7 +693,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ev_ms / args.steps,
+        "ms_per_step": evg_ms / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -685,13 +705,14 @@ def main():
                    "dt": w["dt"], "params": w["params"]},
         "roofline": {"bound": "hbm", "kernel": dom, "scope": "the dominant kernel alone (live launch times)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS if achieved else None, "traffic": measured_traffic(dom),
+                     "frac": achieved / HBM_PEAK_GBPS if achieved else None,
+                     "traffic": measured_traffic(dom, "2d512_s64", variant_of(dom, [grid4], variants)),
                      "avg_launch_ms": dom_avg_ms, "algorithmic_bytes_per_launch": dom_bytes,
-                     "valu": valu_entry(dom, dom_avg_ms), "copy_reference": cref,
+                     "valu": valu_entry(dom, dom_avg_ms, variant_of(dom, [grid4], variants)), "copy_reference": cref,
                      "frac_of_copy": achieved / cref["achieved"] if cref else None},
-        # the whole split step of the timed region and of the graph replay
+        # the whole split step of the timed region, and of the profiled direct launches
         "roofline_whole_step": dict(whole_step_entry(value, [grid4], "c64"),
-                                    frac_graph_replay=whole_step_entry(value_graph, [grid4], "c64")["frac"]),
+                                    frac_direct_launches=whole_step_entry(value_direct, [grid4], "c64")["frac"]),
         # working sets beyond the 256 MB last-level cache: every pass of the
         # 2.4 GB 2D batch and of the 3 GiB 3D batch
         "rooflines_cache_cold": {
@@ -701,7 +722,7 @@ def main():
                          "passes": others["3d_256_s8_c64"]["rooflines"]}},
         "autotuned_variants": variants,
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
-        "graph_replay": {"value": value_graph, "unit": "site-steps/s", "ms_per_step": evg_ms / args.steps},
+        "direct_launches_profiled": {"value": value_direct, "unit": "site-steps/s", "ms_per_step": ev_ms / args.steps},
         "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
                  "ms_per_step": ev64 / args.fp64_steps},
         "speedup_fp32_vs_fp64": value / value64,

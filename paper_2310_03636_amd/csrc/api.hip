@@ -297,6 +297,11 @@ struct spin1_ctx {
   }
 };
 
+LaunchTiming& spin1::launch_timing() {
+  static thread_local LaunchTiming lt;
+  return lt;
+}
+
 namespace {
 
 int check_ctx(spin1_ctx* ctx, bool need_bound) {
@@ -326,20 +331,45 @@ hipEvent_t next_event(spin1_ctx* ctx) {
   return ctx->ev_pool[ctx->ev_used++];
 }
 
-// Brackets one launch with events when profiling is on.
+// Times the launches of its scope when profiling is on.  A scope with one
+// kernel launch is timed by the kernel's own begin and end (the events handed
+// to launch_kernel); a scope with several by events recorded on the stream
+// before and after it.  ONE: the scope launches exactly one kernel (the step
+// passes), so no events go on the stream, which keeps the profiled steps'
+// launch gaps close to those of unprofiled ones.
 struct Prof {
   spin1_ctx* ctx;
   int kind;
-  hipEvent_t a = nullptr;
-  Prof(spin1_ctx* c, int k) : ctx(c), kind(k) {
-    if (ctx->prof && (a = next_event(ctx))) (void)hipEventRecord(a, ctx->stream);
+  bool one;
+  hipEvent_t a = nullptr, b = nullptr, ka = nullptr, kb = nullptr;
+  int64_t first = 0;
+  bool on = false;
+  Prof(spin1_ctx* c, int k, bool one_launch = false) : ctx(c), kind(k), one(one_launch) {
+    if (!ctx->prof) return;
+    ka = next_event(ctx);
+    kb = next_event(ctx);
+    if (!one) {
+      a = next_event(ctx);
+      b = next_event(ctx);
+    }
+    if (!ka || !kb || (!one && (!a || !b))) return;
+    on = true;
+    if (!one) (void)hipEventRecord(a, ctx->stream);
+    LaunchTiming& lt = launch_timing();
+    lt.start = ka;
+    lt.stop = kb;
+    first = lt.launches;
   }
   ~Prof() {
-    if (!a) return;
-    hipEvent_t b = next_event(ctx);
-    if (!b) return;
-    (void)hipEventRecord(b, ctx->stream);
-    ctx->rec.push_back(ProfRecord{kind, a, b});
+    if (!on) return;
+    LaunchTiming& lt = launch_timing();
+    const int64_t n = lt.launches - first;
+    lt.start = lt.stop = nullptr;  // unused when the scope launched nothing
+    if (!one) (void)hipEventRecord(b, ctx->stream);
+    if (n == 1)
+      ctx->rec.push_back(ProfRecord{kind, ka, kb});
+    else if (n > 1 && !one)
+      ctx->rec.push_back(ProfRecord{kind, a, b});
   }
 };
 
@@ -446,14 +476,14 @@ int enqueue_group_rest(spin1_ctx* ctx, const GroupState& G, void* field, double 
     sa.reverse = pass_reverse(step * G.geo.dim + a);
     sa.tick = step;
     {
-      Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS);
+      Prof pr(ctx, a == 1 ? SPIN1_K_YPASS : SPIN1_K_ZPASS, true);
       e = launch_spass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[a], sa, variant_of(ctx, 1, G.geo.n[a]));
     }
     if (e != hipSuccess) return hip_fail(e, a == 1 ? "y-pass" : "z-pass");
   }
   if (G.geo.dim > 1 && tau_close != 0.0) {
     {
-      Prof pr(ctx, SPIN1_K_LOCAL);
+      Prof pr(ctx, SPIN1_K_LOCAL, true);
       e = launch_local(ctx->stream, ctx->dbl, field, G.geo.S, G.geo.sites, tau_close, ctx->p.c0, ctx->p.c1, G.pot);
     }
     if (e != hipSuccess) return hip_fail(e, "closing local update");
@@ -474,7 +504,7 @@ int enqueue_group_step(spin1_ctx* ctx, const GroupState& G, void* field, double 
   xa.tau_post = G.geo.dim == 1 ? tau_close : 0.0;
   hipError_t e;
   {
-    Prof pr(ctx, SPIN1_K_XPASS);
+    Prof pr(ctx, SPIN1_K_XPASS, true);
     e = launch_xpass(ctx->stream, ctx->dbl, MODE_STEP, G.geo.n[0], xa, variant_of(ctx, 0, G.geo.n[0]));
   }
   if (e != hipSuccess) return hip_fail(e, "x-pass");
@@ -505,7 +535,7 @@ int enqueue_group_multi(spin1_ctx* ctx, const GroupState& G, int64_t n, double d
     const int k = int(n - i0 < per ? n - i0 : per);
     hipError_t e;
     {
-      Prof pr(ctx, SPIN1_K_XPASS);
+      Prof pr(ctx, SPIN1_K_XPASS, true);
       e = launch_x1d_multi(ctx->stream, ctx->dbl, G.geo.n[0], xa, k, dt, i0 == 0, i0 + k == n, split_1d(ctx, G));
     }
     if (e != hipSuccess) return hip_fail(e, "1D multi-step pass");
@@ -555,7 +585,7 @@ int enqueue_grouped_x(spin1_ctx* ctx, const std::vector<size_t>& set, double tau
   ga.tick = step;
   hipError_t e;
   {
-    Prof pr(ctx, SPIN1_K_XPASS);
+    Prof pr(ctx, SPIN1_K_XPASS, true);
     e = launch_xpass_grouped(ctx->stream, ctx->dbl, ga);
   }
   if (e != hipSuccess) return hip_fail(e, "grouped x-pass");

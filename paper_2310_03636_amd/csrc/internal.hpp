@@ -1,10 +1,47 @@
 // Internal interface between the C ABI (api.hip) and the kernel units (kernels*.hip).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
+#include <tuple>
+#include <utility>
+
 namespace spin1 {
+
+// Every kernel launch of the library goes through launch_kernel.  While
+// profiling is on, the bracket around a launch (api.hip) hands the thread's
+// next launch a start and a stop event: that launch then goes through
+// hipExtLaunchKernel, which stamps the kernel's own begin and end into them,
+// so the measured time leaves out the dispatch gap that events recorded on
+// the stream around the launch would include.  The arguments are converted
+// to the kernel's parameter types before their addresses are handed over.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int64_t launches = 0;  // launches made by this thread so far
+};
+LaunchTiming& launch_timing();  // the calling thread's
+
+template <typename... P, typename... A>
+hipError_t launch_kernel(void (*kernel)(P...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t st, A&&... args) {
+  static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+  std::tuple<P...> values(std::forward<A>(args)...);
+  void* ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1] = {};
+  std::apply([&ptrs](auto&... v) {
+    int i = 0;
+    ((ptrs[i++] = static_cast<void*>(&v)), ...);
+  }, values);
+  const void* fn = reinterpret_cast<const void*>(kernel);
+  LaunchTiming& lt = launch_timing();
+  lt.launches++;
+  if (lt.start) {
+    hipEvent_t a = lt.start, b = lt.stop;
+    lt.start = lt.stop = nullptr;
+    return hipExtLaunchKernel(fn, grid, block, ptrs, shmem, st, a, b, 0);
+  }
+  return hipLaunchKernel(fn, grid, block, ptrs, shmem, st);
+}
 
 // Geometry of one group: S samples of a dim-dimensional periodic grid,
 // field layout [S][3][Nz][Ny][Nx] (x fastest), n[a] = 1 for a >= dim.

@@ -211,12 +211,12 @@ static hipError_t xpass_n(hipStream_t st, const XPassArgs& a, int variant) {
     const int64_t blocks = (int64_t(a.S) * a.rows + P - 1) / P;
     if constexpr (N >= 2048 || (MODE == MODE_STEP_LOG && N > XCfg<N, Real>::R)) {
       if (MODE == MODE_STEP_LOG || blocks <= device_cus()) {
-        hipLaunchKernelGGL((k_xpass<Real, N, MODE, true>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0,
+        (void)launch_kernel((k_xpass<Real, N, MODE, true>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0,
                            st, a);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
+    (void)launch_kernel((k_xpass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st, a);
     return hipGetLastError();
   }
 }

@@ -385,10 +385,10 @@ hipError_t launch_tables(hipStream_t st, bool dbl, void* ph, void* tw, int n, in
                          double dx) {
   const unsigned blocks = unsigned((n + 255) / 256);
   if (dbl)
-    hipLaunchKernelGGL(k_tables<double>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<double>*>(ph),
+    (void)launch_kernel(k_tables<double>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<double>*>(ph),
                        static_cast<TabEntry<double>*>(tw), n, ncomp, dt, q, dx);
   else
-    hipLaunchKernelGGL(k_tables<float>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<float>*>(ph),
+    (void)launch_kernel(k_tables<float>, dim3(blocks), dim3(256), 0, st, static_cast<TabEntry<float>*>(ph),
                        static_cast<TabEntry<float>*>(tw), n, ncomp, dt, q, dx);
   return hipGetLastError();
 }
@@ -399,10 +399,10 @@ hipError_t launch_init(hipStream_t st, bool dbl, void* psi, const Geom& g, uint6
   const double amp = sqrt(wigner_var / (2.0 * cell));
   const unsigned blocks = grid_for(int64_t(g.S) * 3 * g.sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_init<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), g.S, g.sites,
+    (void)launch_kernel(k_init<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), g.S, g.sites,
                        seed, group, first_sample, amp, sqrt(n0));
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), g.S, g.sites,
+    (void)launch_kernel(k_init<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), g.S, g.sites,
                        seed, group, first_sample, amp, sqrt(n0));
   return hipGetLastError();
 }
@@ -411,10 +411,10 @@ hipError_t launch_local(hipStream_t st, bool dbl, void* psi, int S, int64_t site
                         const double* pot) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites, tau,
+    (void)launch_kernel(k_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites, tau,
                        c0, c1, pot, tau);
   else
-    hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
+    (void)launch_kernel(k_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
                        float(tau), float(c0), float(c1), pot, tau);
   return hipGetLastError();
 }
@@ -423,10 +423,10 @@ hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_
                               double c1, double q, const double* pot) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_paper_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites,
+    (void)launch_kernel(k_paper_local<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(psi), S, sites,
                        dt, c0, c1, q, pot, dt);
   else
-    hipLaunchKernelGGL(k_paper_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
+    (void)launch_kernel(k_paper_local<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(psi), S, sites,
                        float(dt), float(c0), float(c1), float(q), pot, dt);
   return hipGetLastError();
 }
@@ -434,10 +434,10 @@ hipError_t launch_paper_local(hipStream_t st, bool dbl, void* psi, int S, int64_
 hipError_t launch_f_perp(hipStream_t st, bool dbl, const void* psi, int S, int64_t sites, void* out) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_f_perp<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi), S,
+    (void)launch_kernel(k_f_perp<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi), S,
                        sites, static_cast<Cx<double>*>(out));
   else
-    hipLaunchKernelGGL(k_f_perp<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi), S, sites,
+    (void)launch_kernel(k_f_perp<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi), S, sites,
                        static_cast<Cx<float>*>(out));
   return hipGetLastError();
 }
@@ -446,14 +446,14 @@ hipError_t launch_texture(hipStream_t st, bool dbl, const void* psi, int S, int6
                           double* part, double* out) {
   const unsigned blocks = unsigned(int64_t(S) * rows);
   if (dbl)
-    hipLaunchKernelGGL(k_texture_rows<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
+    (void)launch_kernel(k_texture_rows<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
                        rows, sites, n, part);
   else
-    hipLaunchKernelGGL(k_texture_rows<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
+    (void)launch_kernel(k_texture_rows<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
                        rows, sites, n, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_texture_finish, dim3(unsigned(S)), dim3(256), 0, st, part, rows, sites, out);
+  (void)launch_kernel(k_texture_finish, dim3(unsigned(S)), dim3(256), 0, st, part, rows, sites, out);
   return hipGetLastError();
 }
 
@@ -461,17 +461,17 @@ hipError_t launch_bin(hipStream_t st, bool dbl, const void* power, int S, int64_
                       const int32_t* offs, int nbins, double* out) {
   const dim3 grid(unsigned((nbins + 3) / 4), unsigned(S));
   if (dbl)
-    hipLaunchKernelGGL(k_bin<double>, grid, dim3(256), 0, st, static_cast<const double*>(power), sites, perm, offs,
+    (void)launch_kernel(k_bin<double>, grid, dim3(256), 0, st, static_cast<const double*>(power), sites, perm, offs,
                        nbins, out);
   else
-    hipLaunchKernelGGL(k_bin<float>, grid, dim3(256), 0, st, static_cast<const float*>(power), sites, perm, offs,
+    (void)launch_kernel(k_bin<float>, grid, dim3(256), 0, st, static_cast<const float*>(power), sites, perm, offs,
                        nbins, out);
   return hipGetLastError();
 }
 
 hipError_t launch_obs_finish(hipStream_t st, int S, const double* part_x, int64_t rows, const double* part_y,
                              int64_t ny_blocks, const double* part_z, int64_t nz_blocks, double cell, double* obs) {
-  hipLaunchKernelGGL(k_obs_finish, dim3(unsigned(S)), dim3(1024), 0, st, part_x, rows, part_y, ny_blocks, part_z,
+  (void)launch_kernel(k_obs_finish, dim3(unsigned(S)), dim3(1024), 0, st, part_x, rows, part_y, ny_blocks, part_z,
                      nz_blocks, cell, obs);
   return hipGetLastError();
 }
@@ -481,7 +481,7 @@ template <typename Real, int N>
 static hipError_t fft1_n(hipStream_t st, void* f, const void* tw, int64_t pencils) {
   constexpr int P = XCfg<N, Real>::P;
   const int64_t blocks = (pencils + P - 1) / P;
-  hipLaunchKernelGGL((k_fft1_x<Real, N>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st,
+  (void)launch_kernel((k_fft1_x<Real, N>), dim3(unsigned(blocks)), dim3(XCfg<N, Real>::THREADS), 0, st,
                      static_cast<Cx<Real>*>(f), static_cast<const TabEntry<Real>*>(tw), pencils);
   return hipGetLastError();
 }
@@ -512,7 +512,7 @@ int adj_local_blocks(int S, int64_t sites) { return int(grid_for(int64_t(S) * si
 template <typename Real, int KIND>
 static void adj_local_t(hipStream_t st, unsigned blocks, const void* state, void* h, int S, int64_t sites, double tau,
                         double c0, double c1, double dt, double* part) {
-  hipLaunchKernelGGL((k_adj_local<Real, KIND>), dim3(blocks), dim3(256), 0, st, static_cast<const Cx<Real>*>(state),
+  (void)launch_kernel((k_adj_local<Real, KIND>), dim3(blocks), dim3(256), 0, st, static_cast<const Cx<Real>*>(state),
                      static_cast<Cx<Real>*>(h), S, sites, Real(tau), Real(c0), Real(c1), dt, part);
 }
 
@@ -537,7 +537,7 @@ hipError_t launch_adj_local(hipStream_t st, bool dbl, int kind, const void* stat
 }
 
 hipError_t launch_adj_accum(hipStream_t st, const double* part, int nblocks, double* acc) {
-  hipLaunchKernelGGL(k_adj_accum, dim3(1), dim3(256), 0, st, part, nblocks, acc);
+  (void)launch_kernel(k_adj_accum, dim3(1), dim3(256), 0, st, part, nblocks, acc);
   return hipGetLastError();
 }
 
@@ -545,10 +545,10 @@ hipError_t launch_adj_spectrum(hipStream_t st, bool dbl, void* f, const Geom& g,
                                const double* dl_dbins) {
   const unsigned blocks = grid_for(int64_t(g.S) * g.sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_adj_spectrum<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(f), g.S,
+    (void)launch_kernel(k_adj_spectrum<double>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<double>*>(f), g.S,
                        g.sites, g.dim, g.n[0], g.n[1], g.n[2], offs, nbins, dl_dbins);
   else
-    hipLaunchKernelGGL(k_adj_spectrum<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(f), g.S,
+    (void)launch_kernel(k_adj_spectrum<float>, dim3(blocks), dim3(256), 0, st, static_cast<Cx<float>*>(f), g.S,
                        g.sites, g.dim, g.n[0], g.n[1], g.n[2], offs, nbins, dl_dbins);
   return hipGetLastError();
 }
@@ -556,10 +556,10 @@ hipError_t launch_adj_spectrum(hipStream_t st, bool dbl, void* f, const Geom& g,
 hipError_t launch_adj_seed(hipStream_t st, bool dbl, const void* psi, const void* hf, void* h, int S, int64_t sites) {
   const unsigned blocks = grid_for(int64_t(S) * sites, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_adj_seed<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
+    (void)launch_kernel(k_adj_seed<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(psi),
                        static_cast<const Cx<double>*>(hf), static_cast<Cx<double>*>(h), S, sites);
   else
-    hipLaunchKernelGGL(k_adj_seed<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
+    (void)launch_kernel(k_adj_seed<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(psi),
                        static_cast<const Cx<float>*>(hf), static_cast<Cx<float>*>(h), S, sites);
   return hipGetLastError();
 }
@@ -567,10 +567,10 @@ hipError_t launch_adj_seed(hipStream_t st, bool dbl, const void* psi, const void
 hipError_t launch_conj(hipStream_t st, bool dbl, const void* in, void* out, int64_t n) {
   const unsigned blocks = grid_for(n, 256);
   if (dbl)
-    hipLaunchKernelGGL(k_conj<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(in),
+    (void)launch_kernel(k_conj<double>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<double>*>(in),
                        static_cast<Cx<double>*>(out), n);
   else
-    hipLaunchKernelGGL(k_conj<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(in),
+    (void)launch_kernel(k_conj<float>, dim3(blocks), dim3(256), 0, st, static_cast<const Cx<float>*>(in),
                        static_cast<Cx<float>*>(out), n);
   return hipGetLastError();
 }

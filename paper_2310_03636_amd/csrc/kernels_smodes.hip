@@ -99,7 +99,7 @@ static hipError_t spass_n(hipStream_t st, const SPassArgs& a, int variant) {
     constexpr int TX = SCfg<N, Real>::TX;
     if (a.inner % TX != 0) return hipErrorInvalidValue;
     const int64_t blocks = a.nfield * a.outer * (a.inner / TX);
-    hipLaunchKernelGGL((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
+    (void)launch_kernel((k_spass<Real, N, MODE>), dim3(unsigned(blocks)), dim3(SCfg<N, Real>::THREADS), 0, st, a);
     return hipGetLastError();
   }
 }

@@ -103,7 +103,7 @@ static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
   b.lg_tiles = ilog2(a.inner / TX);
   b.lg_outer = ilog2(a.outer);
   const int64_t grid = stream_grid(k_spass_stream<Real, N, V, PLAIN>, SCfg<N, Real, V>::THREADS, blocks);
-  hipLaunchKernelGGL((k_spass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0,
+  (void)launch_kernel((k_spass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0,
                      st, b, blocks);
   return hipGetLastError();
 }

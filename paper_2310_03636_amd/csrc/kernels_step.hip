@@ -503,12 +503,12 @@ static hipError_t xpass_grouped_t(hipStream_t st, const XGroupArgs& a) {
   if constexpr (sizeof(Real) == 4) {
     if (a.dither) {
       const int64_t grid = stream_grid(k_xpass_grouped<Real, true>, GroupedX<Real>::THREADS, a.item_end);
-      hipLaunchKernelGGL((k_xpass_grouped<Real, true>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
+      (void)launch_kernel((k_xpass_grouped<Real, true>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
       return hipGetLastError();
     }
   }
   const int64_t grid = stream_grid(k_xpass_grouped<Real, false>, GroupedX<Real>::THREADS, a.item_end);
-  hipLaunchKernelGGL((k_xpass_grouped<Real, false>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
+  (void)launch_kernel((k_xpass_grouped<Real, false>), dim3(unsigned(grid)), dim3(GroupedX<Real>::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
@@ -521,12 +521,12 @@ static hipError_t x1d_multi_n(hipStream_t st, const XPassArgs& a, int K, double 
                               bool split) {
   // the latency form where its LDS fits (every size but 4096), else the pencil form
   if (split && SplitCfg<N>::template fits<Real>())
-    hipLaunchKernelGGL((k_x1d_split<Real, N>), dim3(unsigned(a.S)), dim3(SplitCfg<N>::THREADS), 0, st, a, K, dt,
+    (void)launch_kernel((k_x1d_split<Real, N>), dim3(unsigned(a.S)), dim3(SplitCfg<N>::THREADS), 0, st, a, K, dt,
                        int(open_half), int(close_half));
   else if (!MultiCfg<N, Real>::fits())
     return hipErrorInvalidValue;
   else
-    hipLaunchKernelGGL((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
+    (void)launch_kernel((k_x1d_multi<Real, N>), dim3(unsigned(a.S)), dim3(MultiCfg<N, Real>::T), 0, st, a, K, dt,
                        int(open_half), int(close_half));
   return hipGetLastError();
 }

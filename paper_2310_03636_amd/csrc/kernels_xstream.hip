@@ -128,7 +128,7 @@ static hipError_t xpass_stream_v(hipStream_t st, const XPassArgs& a) {
   XPassArgs b = a;
   b.lg_rows = ilog2(a.rows);
   const int64_t grid = stream_grid(k_xpass_stream<Real, N, V, PLAIN, POT>, XCfg<N, Real, V>::THREADS, blocks);
-  hipLaunchKernelGGL((k_xpass_stream<Real, N, V, PLAIN, POT>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS),
+  (void)launch_kernel((k_xpass_stream<Real, N, V, PLAIN, POT>), dim3(unsigned(grid)), dim3(XCfg<N, Real, V>::THREADS),
                      0, st, b, blocks);
   return hipGetLastError();
 }
