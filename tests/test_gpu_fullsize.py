@@ -115,6 +115,30 @@ def test_1d_4096_250_runs_fp64_full_size(lib):
         assert rel(got[i], ref[i]) < 1e-12, s
 
 
+@pytest.mark.timeout(600)
+def test_1d_4096_250_runs_100_steps_against_oracle(lib):
+    """The paper's 1D production shape in the benchmark's launch
+    configuration (up to 64 steps per launch with the samples on chip,
+    captured graph): 100 split steps of dt = 0.01, first, middle and last
+    sample against the oracle run on those samples alone, complex128 within
+    1e-10 and complex64 within 1e-4."""
+    import torch
+
+    g = (1, (4096,), 0.5, 250)
+    which = [0, 123, 249]
+    ref = oracle_samples(1006, g, P2, 0, which, 100, 0.01)
+    for dtype, tol in (("c128", 1e-10), ("c64", 1e-4)):
+        sim = lib.Sim([g], P2, dtype=dtype)
+        sim.init_wigner(1006)
+        sim.autotune(reps=1)
+        sim.step(100, 0.01)
+        got = sim.field_tensor(0)[which].to(torch.complex128).cpu().numpy()
+        sim.close()
+        errs = [rel(got[i], ref[i]) for i in range(len(which))]
+        print("1D 4096 x 250, 100 steps, %s: %s" % (dtype, ", ".join("%.2e" % e for e in errs)))
+        assert max(errs) < tol, (dtype, errs)
+
+
 @pytest.mark.timeout(900)
 def test_2d_512_64_samples_100_steps_against_oracle(lib):
     """The headline workload (512^2 x 64) in the benchmark's launch
