@@ -337,9 +337,14 @@ enum spin1_kernel_kind {
   SPIN1_K_COUNT = 8
 };
 
-/* Profiling: when enabled, every kernel launch is bracketed by two HIP events
- * on the context's stream.  spin1_profile_read synchronises the stream, adds
- * the elapsed times per kind into ms[kind] and the launch counts into
+/* Profiling: when enabled, every library operation that launches kernels is
+ * timed per kind.  An operation with one kernel launch (every step pass) is
+ * timed by that kernel's own begin and end (two HIP events handed to
+ * hipExtLaunchKernel); one with several launches by two HIP events recorded on
+ * the context's stream before and after them.  While profiling is on, calls
+ * run as direct launches on the context's stream (no graphs, no side
+ * streams).  spin1_profile_read synchronises the stream, adds the elapsed
+ * times per kind into ms[kind] and the counts of timed operations into
  * launches[kind] (arrays of n_kinds <= SPIN1_K_COUNT entries, overwritten),
  * and clears the record.  Events are created on first use and reused. */
 SPIN1_API int spin1_profile_enable(spin1_ctx* ctx, int32_t enable);
