@@ -343,9 +343,24 @@ struct Prof {
   bool one;
   hipEvent_t a = nullptr, b = nullptr, ka = nullptr, kb = nullptr;
   int64_t first = 0;
-  bool on = false;
+  bool on = false, nested = false;
+  LaunchTiming outer;
   Prof(spin1_ctx* c, int k, bool one_launch = false) : ctx(c), kind(k), one(one_launch) {
     if (!ctx->prof) return;
+    // inside another scope (not done today) this one is timed on the stream,
+    // and the outer scope's launch events are put back at its end
+    if (launch_timing().start) {
+      one = false;
+      a = next_event(ctx);
+      b = next_event(ctx);
+      if (!a || !b) return;
+      on = true;
+      nested = true;
+      outer = launch_timing();
+      launch_timing().start = launch_timing().stop = nullptr;
+      (void)hipEventRecord(a, ctx->stream);
+      return;
+    }
     ka = next_event(ctx);
     kb = next_event(ctx);
     if (!one) {
@@ -362,6 +377,13 @@ struct Prof {
   }
   ~Prof() {
     if (!on) return;
+    if (nested) {
+      (void)hipEventRecord(b, ctx->stream);
+      ctx->rec.push_back(ProfRecord{kind, a, b});
+      launch_timing().start = outer.start;
+      launch_timing().stop = outer.stop;
+      return;
+    }
     LaunchTiming& lt = launch_timing();
     const int64_t n = lt.launches - first;
     lt.start = lt.stop = nullptr;  // unused when the scope launched nothing
