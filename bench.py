@@ -713,7 +713,7 @@ def main():
                                "reductions, dt=0.02; step = 100 split steps + 1 structure-factor snapshot",
                    "grid": list(w["n"]), "samples": w["samples"], "split_steps_per_step": w["split_steps"],
                    "dt": w["dt"], "params": w["params"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "scope": "the dominant kernel alone, each launch timed by its own begin and end in the timed steps",
+        "roofline": {"bound": "hbm", "kernel": dom, "scope": "the dominant kernel alone, each launch timed by its own begin and end in a profiled run of the same steps",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS if achieved else None,
                      "traffic": measured_traffic(dom, "2d512_s64", variant_of(dom, [grid4], variants)),
