@@ -39,6 +39,17 @@ __device__ __forceinline__ Cx<Real> cmulc(Cx<Real> a, Cx<Real> b) {
 }
 template <typename Real>
 __device__ __forceinline__ Real norm2(Cx<Real> a) { return a.re * a.re + a.im * a.im; }
+// a p + sign b conj(q) (sign = +1 or -1) as one chain of fused multiply-adds
+// per part: one product and three FMAs, each part rounded once at its end
+template <int SIGN, typename Real>
+__device__ __forceinline__ Cx<Real> mul_add_conj(Cx<Real> a, Cx<Real> p, Cx<Real> b, Cx<Real> q) {
+  static_assert(SIGN == 1 || SIGN == -1, "sign");
+  const Real sb = Real(SIGN);
+  // b conj(q) = (b.re q.re + b.im q.im) + i (b.im q.re - b.re q.im)
+  const Real re = fma(a.re, p.re, fma(-a.im, p.im, sb * fma(b.re, q.re, b.im * q.im)));
+  const Real im = fma(a.re, p.im, fma(a.im, p.re, sb * fma(b.im, q.re, -(b.re * q.im))));
+  return {re, im};
+}
 
 // ---------------------------------------------------------------------------
 // Table entries (twiddles, phase factors).  They are computed in FP64; the
@@ -387,6 +398,23 @@ __device__ __forceinline__ float cos_series(float u) {
   return fmaf(u, q, 1.0f);
 }
 
+// The same series one term shorter, for |y| < 0.52 (u < 0.27): sinc to u^3
+// (remainder below 1.5e-8 relative) and cos to u^4 (below 4e-10 absolute).
+// The common path of the local update takes these; its arguments are small
+// (c1 tau |F| / 2 and c0 n tau).
+constexpr float kShortSeriesU = 0.27f;
+__device__ __forceinline__ float sinc_series_short(float u) {
+  float p = fmaf(u, -1.0f / 5040.0f, 1.0f / 120.0f);
+  p = fmaf(u, p, -1.0f / 6.0f);
+  return fmaf(u, p, 1.0f);
+}
+__device__ __forceinline__ float cos_series_short(float u) {
+  float q = fmaf(u, 1.0f / 40320.0f, -1.0f / 720.0f);
+  q = fmaf(u, q, 1.0f / 24.0f);
+  q = fmaf(u, q, -0.5f);
+  return fmaf(u, q, 1.0f);
+}
+
 struct SinCos {
   float s, c;
 };
@@ -422,9 +450,9 @@ __device__ __forceinline__ SinCos sincos_reduced(float y) {
 // sin(y), cos(y) from y itself (single precision)
 __device__ __forceinline__ void sincos_small(float y, float* s, float* c) {
   const float u = y * y;
-  if (u < 0.61685028f) {  // |y| < pi/4
-    *s = y * sinc_series(u);
-    *c = cos_series(u);
+  if (u < kShortSeriesU) {  // |y| < 0.52; beyond, the reduction (k = 0 up to pi/4) and full series
+    *s = y * sinc_series_short(u);
+    *c = cos_series_short(u);
   } else {
     const SinCos r = sincos_reduced(y);
     *s = r.s;
@@ -435,9 +463,9 @@ __device__ __forceinline__ void sincos_small(float y, float* s, float* c) {
 // sinc(y) and cos(y) from u = y^2 >= 0 (single precision): no square root on
 // the common path
 __device__ __forceinline__ void sinc_cos_from_square(float u, float* sc, float* c) {
-  if (u < 0.61685028f) {
-    *sc = sinc_series(u);
-    *c = cos_series(u);
+  if (u < kShortSeriesU) {
+    *sc = sinc_series_short(u);
+    *c = cos_series_short(u);
   } else {
     const float y = sqrtf(u);
     const SinCos r = sincos_reduced(y);
@@ -573,9 +601,9 @@ __device__ __forceinline__ void local_update(Cx<Real>* psi, Real tau, Real c0, R
   const Cx<Real> a = {cp + (cp * cm1 - sp * ns), -sp - (sp * cm1 + cp * ns)};
   const Cx<Real> b = Cx<Real>{cp, -sp} * Cx<Real>{s * th.im, -s * th.re};
   const Cx<Real> p1 = psi[0], p0 = psi[1], pm = psi[2];
-  psi[0] = a * p1 - b * conj(pm);
-  psi[1] = a * p0 + b * conj(p0);
-  psi[2] = a * pm - b * conj(p1);
+  psi[0] = mul_add_conj<-1>(a, p1, b, pm);
+  psi[1] = mul_add_conj<1>(a, p0, b, p0);
+  psi[2] = mul_add_conj<-1>(a, pm, b, p1);
 }
 
 // ---------------------------------------------------------------------------
