@@ -116,6 +116,32 @@ def test_1d_4096_250_runs_fp64_full_size(lib):
 
 
 @pytest.mark.timeout(600)
+def test_paper_scheme_2d_512_64_samples_full_size(lib):
+    """The paper's own Lie scheme (Eqs. (3)-(5)) on the 512^2 x 64 batch in the
+    benchmark's launch configuration for that scheme (autotuned variants,
+    captured graph): 5 steps of dt = 0.02 in one call, the first and last
+    sample against the oracle's literal steps run on those samples alone."""
+    import torch
+
+    g = (2, (512, 512), 0.5, 64)
+    which = [0, 63]
+    og = O.Grid(2, (512, 512), 0.5, 64)
+    psi = O.init_wigner(1002, og, oparams(P2), group=0, samples=which)
+    sub = O.Grid(2, (512, 512), 0.5, len(which))
+    ref = O.evolve(psi, 5, 0.02, oparams(P2), sub, step=O.paper_step)
+    for dtype, tol in (("c128", 1e-12), ("c64", 2e-5)):
+        sim = lib.Sim([g], P2, dtype=dtype)
+        sim.init_wigner(1002)
+        sim.autotune(reps=1)
+        sim.set_option(lib.OPT_SCHEME, lib.SCHEME_PAPER)
+        sim.step(5, 0.02)
+        got = sim.field_tensor(0)[which].to(torch.complex128).cpu().numpy()
+        sim.close()
+        for i, s in enumerate(which):
+            assert rel(got[i], ref[i]) < tol, (dtype, s)
+
+
+@pytest.mark.timeout(600)
 def test_1d_4096_250_runs_100_steps_against_oracle(lib):
     """The paper's 1D production shape in the benchmark's launch
     configuration (up to 64 steps per launch with the samples on chip,
