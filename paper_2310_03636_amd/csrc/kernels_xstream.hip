@@ -26,10 +26,18 @@ namespace spin1 {
 // the hi+lo form, and no rounding that repeats identically in every step
 // POT: the group has a trap potential (a separate instantiation, so that the
 // common case keeps its register budget)
+// Wavefronts per SIMD the register allocation must allow: three for the
+// single-precision dithered-table form up to 1024 points (168 VGPRs; at 1024
+// points one register is reloaded once per item, and the 128-thread variant 1
+// cannot reach three), else whatever the allocation gives.
+template <typename Real, int N, int V, bool PLAIN, bool POT>
+constexpr int xstream_waves() {
+  return (PLAIN && !POT && sizeof(Real) == 4 && (N <= 512 || (N == 1024 && V != 1))) ? 3 : 1;
+}
+
 template <typename Real, int N, int V, bool PLAIN, bool POT = false, bool ENABLED = XCfg<N, Real, V>::STREAM>
 __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
-    amdgpu_waves_per_eu((PLAIN && !POT && sizeof(Real) == 4 && N <= 512) ? 3 : 1))) void k_xpass_stream(XPassArgs a,
-                                                                                                       int64_t groups) {
+    amdgpu_waves_per_eu(xstream_waves<Real, N, V, PLAIN, POT>()))) void k_xpass_stream(XPassArgs a, int64_t groups) {
  if constexpr (ENABLED) {
   using C = Cx<Real>;
   constexpr int R = XCfg<N, Real, V>::R, T = XCfg<N, Real, V>::T, P = XCfg<N, Real, V>::P;

@@ -716,7 +716,7 @@ def test_graph_option_validation(lib):
 
 
 # ------------------------------------------------------------------ step-pass variants and autotuning
-@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 128), (512, 512), (16, 512), (256, 1024), (4096, 16)])
+@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 128), (512, 512), (16, 512), (256, 1024), (1024, 64), (4096, 16)])
 def test_every_step_variant_matches_oracle(lib, nx, ny):
     grid = (2, (nx, ny), 0.5, 2)
     og = O.Grid(2, (nx, ny), 0.5, 2)
