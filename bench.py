@@ -390,13 +390,19 @@ def host_workers():
     return max(1, min(n, 16))
 
 
-def oracle_baseline(budget_s=12.0):
+UNEVEN_GROUPS = [(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16), (2, (1024, 1024), 0.5, 4)]
+
+
+def oracle_baseline(budget_s=12.0, with_3d=False):
     """The FP64 oracle as it stands, on the host cores, in worker processes of
     one thread each (spawned, with the BLAS/OpenMP thread counts set to 1):
     (a) the main workload, one 512 x 512 sample per worker, steps until
     budget_s; the rate is the sum of the workers' own rates (their timed loops
     overlap); (b) the same sample on one thread alone; (c) the 1D 256 x 4
-    double-precision workload in full (1000 steps) on one thread."""
+    double-precision workload in full (1000 steps) on one thread; (d) one
+    sample of each group of the uneven batch, one worker each, steps until a
+    third of budget_s (at least one step); (e) with with_3d, one 256^3 sample
+    for one step (minutes of CPU time, so not in the default run)."""
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
 
@@ -415,6 +421,15 @@ def oracle_baseline(budget_s=12.0):
             one = ex.submit(oracle_run, main_job(0, budget_s)).result()
             c1 = ex.submit(oracle_run, (1, (256,), 0.5, 4, dict(c0=1.0, c1=-0.1, q=0.09), 0.01, 1001,
                                         [0, 1, 2, 3], 10 ** 9, 1000)).result()
+        uneven_params = dict(c0=1.0, c1=-0.1, q=0.09)
+        with ProcessPoolExecutor(max_workers=min(workers, len(UNEVEN_GROUPS)), mp_context=ctx) as ex:
+            c4 = list(ex.map(oracle_run, [(g[0], g[1], g[2], g[3], uneven_params, 0.02, 1004, [0], budget_s / 3,
+                                           10 ** 9) for g in UNEVEN_GROUPS]))
+        c3 = None
+        if with_3d:
+            with ProcessPoolExecutor(max_workers=1, mp_context=ctx) as ex:
+                c3 = ex.submit(oracle_run, (3, (256, 256, 256), 0.5, 8, dict(c0=1.0, c1=-0.05, q=0.025), 0.02, 1003,
+                                            [0], 0.0, 1)).result()
     finally:
         for k, v in saved.items():
             if v is None:
@@ -429,7 +444,18 @@ def oracle_baseline(budget_s=12.0):
             "single_thread": {"value": one[0] / one[1], "unit": "site-steps/s", "steps": one[2],
                               "seconds": one[1]},
             "config_1d_256_s4_c128_full": {"value": c1[0] / c1[1], "unit": "site-steps/s", "steps": c1[2],
-                                            "seconds": c1[1], "threads": 1}}
+                                            "seconds": c1[1], "threads": 1},
+            # the whole batch's site-steps over the core-seconds one sample of
+            # each group takes, per sample-step in proportion to its group
+            "config_uneven_one_sample_per_group": {
+                "value": sum(g[3] * r[0] / r[2] for g, r in zip(UNEVEN_GROUPS, c4))
+                / sum(g[3] * r[1] / r[2] for g, r in zip(UNEVEN_GROUPS, c4)),
+                "unit": "site-steps/s per core", "groups": [
+                    {"grid": list(g[1]), "steps": r[2], "seconds": r[1], "value": r[0] / r[1]}
+                    for g, r in zip(UNEVEN_GROUPS, c4)]},
+            "config_3d_256_s8_one_sample_one_step": (
+                {"value": c3[0] / c3[1], "unit": "site-steps/s", "steps": c3[2], "seconds": c3[1], "threads": 1}
+                if c3 else "not run by default (one oracle step of a 256^3 sample takes minutes); --cpu-3d runs it")}
 
 
 PROFILE_WORKLOADS = {
@@ -631,6 +657,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-3d", action="store_true",
+                    help="also time one oracle step of one 256^3 sample (minutes of CPU time)")
     ap.add_argument("--profile-pass", nargs="?", const="2d512_s64", default=None,
                     choices=sorted(PROFILE_WORKLOADS),
                     help="short run of a workload for rocprofv3 counter passes (no JSON line)")
@@ -694,7 +722,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = oracle_baseline(args.cpu_budget)
+        cpu = oracle_baseline(args.cpu_budget, with_3d=args.cpu_3d)
 
     line = {
         "metric": "site-steps/s, spin-1 split-step (FP32 vs FP64 at stated err); HBM GB/s",
