@@ -874,6 +874,41 @@ def test_uniform_polar_and_ferromagnet_on_gpu(lib, dtype, tol):
     assert np.max(np.abs(out[:, 1:])) < tol
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("grid", [(1, (4096,), 0.5, 3), (2, (512, 64), 0.5, 2), (3, (32, 16, 64), 0.5, 2)])
+def test_vacuum_stays_empty(lib, grid, dtype):
+    """The empty field (no condensate, no noise) is a fixed point of every
+    sub-step: after steps in every kernel form it is exactly zero, and so are
+    its observables and structure factor (no NaN from the local update's
+    0/0 limits at n = |F| = 0)."""
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    zero = np.zeros(og.shape, complex)
+    for per_launch in (1, 64):
+        sim = lib.Sim([grid], P1, dtype=dtype)
+        sim.set_option(lib.OPT_STEPS_PER_LAUNCH_1D, per_launch)
+        sim.set_fields([zero])
+        sim.step(9, 0.02)
+        assert np.array_equal(sim.fields()[0], zero), per_launch
+        assert np.array_equal(sim.observables(), np.zeros((grid[3], 3)))
+        _, mean, _, _, per = sim.structure_factor()
+        assert np.array_equal(per, np.zeros_like(per)) and np.all(mean == 0)
+        sim.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 1e-6)])
+@pytest.mark.parametrize("grid", [(1, (4096,), 0.5, 3), (2, (512, 64), 0.5, 2), (3, (32, 16, 64), 0.5, 2)])
+def test_zero_time_step_is_the_identity(lib, grid, dtype, tol):
+    """dt = 0: every phase is 1, so a step returns the field up to the
+    rounding of a forward and an inverse transform per axis."""
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(29, og.shape, noise=0.4)
+    sim = lib.Sim([grid], P1, dtype=dtype)
+    sim.set_fields([psi0])
+    sim.step(3, 0.0)
+    assert rel(sim.fields()[0], psi0) < tol
+    sim.close()
+
+
 @pytest.mark.parametrize("dtype,tol", [("c128", 1e-13), ("c64", 2e-6)])
 def test_out_of_line_sincos_under_divergence(lib, dtype, tol):
     """A sample with one site of huge density shares a wavefront with a normal
