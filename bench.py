@@ -465,7 +465,9 @@ PROFILE_WORKLOADS = {
     "uneven": ([(1, (4096,), 0.5, 128), (2, (256, 256), 0.5, 32), (2, (512, 512), 0.5, 16),
                 (2, (1024, 1024), 0.5, 4)], dict(c0=1.0, c1=-0.1, q=0.09), 0.02),
     "1d4096_s250": ([(1, (4096,), 0.5, 250)], dict(c0=1.0, c1=-0.1, q=0.09), 0.01),
+    "2d512_s64_c128": ([(2, (512, 512), 0.5, 64)], dict(c0=1.0, c1=-0.1, q=0.09), 0.02),
 }
+PROFILE_DTYPE = {"1d4096_s250": "c128", "2d512_s64_c128": "c128"}
 
 
 def profile_pass(workload="2d512_s64"):
@@ -479,7 +481,7 @@ def profile_pass(workload="2d512_s64"):
     from paper_2310_03636_amd import spin1
 
     groups, params, dt = PROFILE_WORKLOADS[workload]
-    sim = spin1.Sim(groups, dict(params, n0=1.0, wigner_var=0.5), dtype="c128" if workload == "1d4096_s250" else "c64")
+    sim = spin1.Sim(groups, dict(params, n0=1.0, wigner_var=0.5), dtype=PROFILE_DTYPE.get(workload, "c64"))
     sim.init_wigner(1002)
     variants = sim.autotune(reps=2)  # the same choice as the timed run
     sim.set_option(spin1.OPT_GRAPHS, 0)
@@ -587,6 +589,7 @@ def kernel_source_hash():
 
 
 TRAFFIC_FILES = {"2d512_s64": "traffic_xpass_ypass_2d512_s64.md",
+                 "2d512_s64_c128": "traffic_xpass_ypass_2d512_s64_c128.md",
                  "2d512_s384": "traffic_xpass_ypass_2d512_s384.md",
                  "3d256_s8": "traffic_xpass_ypass_zpass_3d256_s8.md"}
 
@@ -710,9 +713,16 @@ def main():
 
     sim64, wall64, ev64, _ = run_gpu("c128", args.fp64_steps, 1, profile=False)
     value64 = per_step_site_steps * args.fp64_steps / (ev64 / 1e3)
+    variants64 = sim64.variants
     sim64.close()
     del sim64
     torch.cuda.empty_cache()
+    # the double-precision passes timed one by one (two profiled steps)
+    simp, _, _, prof64 = run_gpu("c128", 2, 0, profile=True)
+    simp.close()
+    del simp
+    torch.cuda.empty_cache()
+    rooflines64 = pass_rooflines(prof64, [grid4], "c128", "2d512_s64_c128", variants64)
 
     err = fp32_vs_fp64_error()
     compensated = compensated_tables_run(args.steps)
@@ -762,7 +772,8 @@ def main():
         "kernels_ms": {k: {"total_ms": v[0], "launches": v[1], "avg_ms": v[0] / v[1]} for k, v in kinds.items()},
         "direct_launches_profiled": {"value": value_direct, "unit": "site-steps/s", "ms_per_step": ev_ms / args.steps},
         "fp64": {"value": value64, "unit": "site-steps/s", "steps": args.fp64_steps,
-                 "ms_per_step": ev64 / args.fp64_steps},
+                 "ms_per_step": ev64 / args.fp64_steps, "variants": variants64,
+                 "whole_step": whole_step_entry(value64, [grid4], "c128"), "rooflines": rooflines64},
         "speedup_fp32_vs_fp64": value / value64,
         "adjoint": adj,
         "other_configs": others,
