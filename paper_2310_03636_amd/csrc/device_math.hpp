@@ -474,8 +474,10 @@ __device__ __forceinline__ void sinc_cos_from_square(float u, float* sc, float* 
   }
 }
 
-// Double precision: the same forms with series to u^8 (remainder below 1e-17
-// relative for |y| <= pi/4) and the library sincos, out of line, beyond.
+// Double precision: Taylor series below |y| = 0.52 (u < 0.27), sinc to u^6
+// (remainder below 8.1e-17 relative) and cos to u^7 (below 1.4e-18), and the
+// library sincos, out of line, beyond (the local update's arguments c1 tau
+// |F| / 2 and c0 n tau stay below it in every workload here).
 // A double constant cannot be an immediate operand of a VALU instruction, and
 // the compiler keeps such constants in vector registers (one pair each, live
 // across the kernel's loops); passed through a scalar register pair at the
@@ -484,19 +486,17 @@ __device__ __forceinline__ double sreg(double c) {
   asm volatile("" : "+s"(c));
   return c;
 }
-__device__ __forceinline__ double sinc_series(double u) {
-  double p = fma(u, sreg(1.0 / 355687428096000.0), sreg(-1.0 / 1307674368000.0));
-  p = fma(u, p, sreg(1.0 / 6227020800.0));
-  p = fma(u, p, sreg(-1.0 / 39916800.0));
+constexpr double kShortSeriesUD = 0.27;
+__device__ __forceinline__ double sinc_series_short(double u) {
+  double p = fma(u, sreg(1.0 / 6227020800.0), sreg(-1.0 / 39916800.0));
   p = fma(u, p, sreg(1.0 / 362880.0));
   p = fma(u, p, sreg(-1.0 / 5040.0));
   p = fma(u, p, sreg(1.0 / 120.0));
   p = fma(u, p, sreg(-1.0 / 6.0));
   return fma(u, p, 1.0);
 }
-__device__ __forceinline__ double cos_series(double u) {
-  double q = fma(u, sreg(1.0 / 20922789888000.0), sreg(-1.0 / 87178291200.0));
-  q = fma(u, q, sreg(1.0 / 479001600.0));
+__device__ __forceinline__ double cos_series_short(double u) {
+  double q = fma(u, sreg(-1.0 / 87178291200.0), sreg(1.0 / 479001600.0));
   q = fma(u, q, sreg(-1.0 / 3628800.0));
   q = fma(u, q, sreg(1.0 / 40320.0));
   q = fma(u, q, sreg(-1.0 / 720.0));
@@ -514,9 +514,9 @@ __device__ __noinline__ SinCosD sincos_lib(double y) {
 }
 __device__ __forceinline__ void sincos_small(double y, double* s, double* c) {
   const double u = y * y;
-  if (u < 0.61685027506808491) {  // |y| < pi/4
-    *s = y * sinc_series(u);
-    *c = cos_series(u);
+  if (u < kShortSeriesUD) {
+    *s = y * sinc_series_short(u);
+    *c = cos_series_short(u);
   } else {
     const SinCosD r = sincos_lib(y);
     *s = r.s;
@@ -524,9 +524,9 @@ __device__ __forceinline__ void sincos_small(double y, double* s, double* c) {
   }
 }
 __device__ __forceinline__ void sinc_cos_from_square(double u, double* sc, double* c) {
-  if (u < 0.61685027506808491) {
-    *sc = sinc_series(u);
-    *c = cos_series(u);
+  if (u < kShortSeriesUD) {
+    *sc = sinc_series_short(u);
+    *c = cos_series_short(u);
   } else {
     const double y = sqrt(u);
     const SinCosD r = sincos_lib(y);

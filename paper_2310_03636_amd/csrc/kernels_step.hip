@@ -192,38 +192,44 @@ k_xpass_grouped(XGroupArgs a) {
 // LDS holds the exchange rows and the twiddles.  Where N is a power of the
 // radix and two rows fit, the exchanges use the two rows in turn, which
 // halves the workgroup barriers (see fft_stages_2row).  In double precision
-// the twiddles are then held as one base value per butterfly and stage (see
-// BaseTwiddles), 9 KB at N = 4096 instead of 64 KB for every power, which is
-// what makes room for the second 72 KB row.  The twiddles are re-read from
+// the twiddles are then held as two base values per butterfly and stage (see
+// BaseTwiddles), 18 KB at N = 4096 instead of 64 KB for every power, which is
+// what makes room for the second 68 KB row.  The twiddles are re-read from
 // LDS in every step: kept in registers across steps (the compiler would hoist
 // them out of the step loop) they would spill.
 // --------------------------------------------------------------------------
 
 // Double precision: the twiddles of the stage with sub-transform size Ns as
-// the one base value w^j per butterfly (w = exp(-2 pi i / (Ns R))), the stages
-// Ns = R, R^2, ..., N/R one after another from entry (Ns - R)/(R - 1).  The
-// powers w^(j r) are formed in registers by products of depth at most three
-// (a few units of FP64 rounding, against one for a table of every power).
+// two base values per butterfly, w^j and w^(2j) (w = exp(-2 pi i / (Ns R))),
+// the stages Ns = R, R^2, ..., N/R one after another from butterfly entry
+// (Ns - R)/(R - 1).  The other powers w^(j r) are formed in registers by
+// products of depth at most two (a few units of FP64 rounding, against one
+// for a table of every power, in a quarter of its space).
 template <int N, int R>
 struct BaseTwiddles {
+  static_assert(R == 8, "powers formed for radix 8");
   const Cx<double>* t;
-  static constexpr int SIZE = (N - R) / (R - 1);
+  static constexpr int BUTTERFLIES = (N - R) / (R - 1);
+  static constexpr int SIZE = 2 * BUTTERFLIES;
   // exponent m of entry i in exp(-2 pi i m / N) (table construction)
   __device__ static __forceinline__ int exponent(int i) {
-    int ns = R;
-    while (i >= ns) {
-      i -= ns;
+    int j = i >> 1, ns = R;
+    while (j >= ns) {
+      j -= ns;
       ns *= R;
     }
-    return i * (N / (ns * R));
+    return ((i & 1) + 1) * j * (N / (ns * R));
   }
 };
 
-template <int R>
-__device__ __forceinline__ void twiddle_powers(Cx<double> (&p)[R], Cx<double> w) {
-  p[1] = w;
-#pragma unroll
-  for (int r = 2; r < R; ++r) p[r] = (r % 2 == 0) ? p[r / 2] * p[r / 2] : p[r / 2 + 1] * p[r / 2];
+__device__ __forceinline__ void twiddle_powers(Cx<double> (&p)[8], Cx<double> w1, Cx<double> w2) {
+  p[1] = w1;
+  p[2] = w2;
+  p[3] = w2 * w1;
+  p[4] = w2 * w2;
+  p[5] = p[4] * w1;
+  p[6] = p[4] * w2;
+  p[7] = p[4] * p[3];
 }
 
 template <int N, int Ns, int R, typename Real>
@@ -234,7 +240,8 @@ __device__ __forceinline__ void apply_twiddles(Cx<Real> (&w)[R], const StagedTwi
 template <int N, int Ns, int R>
 __device__ __forceinline__ void apply_twiddles(Cx<double> (&w)[R], const BaseTwiddles<N, R>& tw, int j) {
   Cx<double> p[R];
-  twiddle_powers<R>(p, tw.t[(Ns - R) / (R - 1) + j]);
+  const Cx<double>* e = tw.t + 2 * ((Ns - R) / (R - 1) + j);
+  twiddle_powers(p, e[0], e[1]);
 #pragma unroll
   for (int r = 1; r < R; ++r) w[r] = w[r] * p[r];
 }
@@ -277,10 +284,13 @@ template <int N, typename Real>
 struct MultiCfg {
   static constexpr int R = N <= 8 ? N : 8;
   static constexpr int T = N / R;
-  static constexpr int SH = sizeof(Real) == 8 ? 3 : 4;  // row padding: one element after every 2^SH
-  static constexpr int ROW = RowPad<N, T, SH>::ROW;
   static constexpr bool POW = N == 8 || N == 64 || N == 512 || N == 4096;  // N a power of R
   static constexpr bool BASE = sizeof(Real) == 8 && POW && N > R;
+  // row padding: one element after every 2^SH (one per 8 for the single
+  // double-precision row; one per 16 where the base-value twiddles share LDS
+  // with two rows, measured equal to one per 8 there)
+  static constexpr int SH = (sizeof(Real) == 8 && !BASE) ? 3 : 4;
+  static constexpr int ROW = RowPad<N, T, SH>::ROW;
   using TW = std::conditional_t<BASE, BaseTwiddles<N, R>, StagedTwiddles<Real, N, R>>;
   using TWE = std::conditional_t<BASE, Cx<double>, TabEntry<Real>>;
   static constexpr int TW_ENTRIES = TW::SIZE > 0 ? TW::SIZE : 1;
