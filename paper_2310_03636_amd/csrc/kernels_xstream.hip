@@ -10,14 +10,9 @@ namespace spin1 {
 // of item i + gridDim.x are already in flight, so HBM traffic overlaps the FFT
 // arithmetic even at one or two resident workgroups per CU.  Every item is
 // owned by exactly one workgroup, so reading the next item early sees the
-// pre-pass state.  The x-pass mostly does not: without the second register
-// set it fits three wavefronts per SIMD instead of two, and the other
-// wavefronts cover its loads (measured 4-6% faster on 256- and 512-point
-// pencils of a 64-sample batch).  Only variant 2 of single-precision
-// 512-point pencils prefetches, at two wavefronts per SIMD: on batches several
-// times the last-level cache (384 samples of 512^2) it measured about 4% faster
-// than the best three-wavefront form, on 64 samples about 6% slower, and the
-// autotuner picks between them per batch.
+// pre-pass state.  The x-pass does not: without the second register set it
+// fits three wavefronts per SIMD instead of two, and the other wavefronts
+// cover its loads (measured 4-6% faster on 256- and 512-point pencils).
 // Consecutive passes walk the items in opposite directions (the host sets
 // `reverse` on every other pass), so each pass starts on the data the one
 // before it wrote last, which the last-level cache still holds.
@@ -34,11 +29,9 @@ namespace spin1 {
 // Wavefronts per SIMD the register allocation must allow: three for the
 // single-precision dithered-table form up to 1024 points (168 VGPRs; at 1024
 // points one register is reloaded once per item, and the 128-thread variant 1
-// cannot reach three), two for the prefetching variant (211 VGPRs), else
-// whatever the allocation gives.
+// cannot reach three), else whatever the allocation gives.
 template <typename Real, int N, int V, bool PLAIN, bool POT>
 constexpr int xstream_waves() {
-  if constexpr (XCfg<N, Real, V>::PREFETCH) return (PLAIN && !POT) ? 2 : 1;
   return (PLAIN && !POT && sizeof(Real) == 4 && (N <= 512 || (N == 1024 && V != 1))) ? 3 : 1;
 }
 
@@ -100,38 +93,20 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
       for (int e = 0; e < R; ++e) dst[m][e] = src[uint32_t(t + e * T)];
     }
   };
-  auto pencil_of = [&](int64_t gg) -> int64_t {
-    int64_t pid = (a.reverse ? groups - 1 - gg : gg) * P + p;
+  int64_t g = blockIdx.x;
+  if (g >= groups) return;
+  for (; g < groups; g += gridDim.x) {
+    int64_t pid = (a.reverse ? groups - 1 - g : g) * P + p;
     if constexpr (T % 64 == 0) pid = wave_uniform(pid);
-    return pid;
-  };
-  auto load_or_zero = [&](C (&dst)[3][R], int64_t pid) {
-    if (pid < npen) {
-      load3(dst, pid);
+    const bool active = pid < npen;
+    C v[3][R];
+    if (active) {
+      load3(v, pid);
     } else {  // a pencil past the end: defined values, never stored
 #pragma unroll
       for (int m = 0; m < 3; ++m)
 #pragma unroll
-        for (int e = 0; e < R; ++e) dst[m][e] = C{Real(0), Real(0)};
-    }
-  };
-  constexpr bool PREFETCH = XCfg<N, Real, V>::PREFETCH && !POT;
-  int64_t g = blockIdx.x;
-  if (g >= groups) return;
-  C nxt[3][R];
-  if constexpr (PREFETCH) load_or_zero(nxt, pencil_of(g));
-  for (; g < groups; g += gridDim.x) {
-    const int64_t pid = pencil_of(g);
-    const bool active = pid < npen;
-    C v[3][R];
-    if constexpr (PREFETCH) {
-#pragma unroll
-      for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int e = 0; e < R; ++e) v[m][e] = nxt[m][e];
-      if (g + gridDim.x < groups) load_or_zero(nxt, pencil_of(g + gridDim.x));
-    } else {
-      load_or_zero(v, pid);
+        for (int e = 0; e < R; ++e) v[m][e] = C{Real(0), Real(0)};
     }
     const double* prow = POT ? a.pot + (pid & (a.rows - 1)) * N : nullptr;
     if (a.tau_pre != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_pre), c0, c1, prow, a.tau_pre);

@@ -13,17 +13,13 @@ namespace spin1 {
 // x-pass: radix R, N/R threads per pencil, P pencils per workgroup; STREAM
 // selects the persistent streaming kernel for the step pass.  V picks one of
 // the step-pass variants the autotuner times: workgroups of about 256 (V = 0),
-// 128 (V = 1) or 512 (V = 2) threads; for single-precision 512-point pencils
-// V = 2 is instead 256 threads that prefetch their next pencils.
+// 128 (V = 1) or 512 (V = 2) threads.
 template <int N, typename Real, int V = 0>
 struct XCfg {
   // radix 16 only where 3 x 16 single-precision values per thread still fit
   static constexpr int R = N <= 8 ? N : ((N <= 1024 || sizeof(Real) == 8) ? 8 : 16);
   static constexpr int T = N / R;
-  // variant 2 of single-precision 512-point pencils: 256 threads with a
-  // prefetch register set for the next item (for batches beyond the cache)
-  static constexpr bool PREFETCH = V == 2 && N == 512 && sizeof(Real) == 4;
-  static constexpr int TARGET = V == 1 ? 128 : (V == 2 && !PREFETCH ? 512 : 256);
+  static constexpr int TARGET = V == 1 ? 128 : (V == 2 ? 512 : 256);
   static constexpr int P = T >= TARGET ? 1 : TARGET / T;
   static constexpr int THREADS = T * P;
   // the streaming kernel keeps twiddles and two phase tables in LDS
