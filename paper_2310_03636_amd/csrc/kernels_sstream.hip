@@ -110,7 +110,8 @@ static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
 
 template <typename Real, int N, bool PLAIN>
 static hipError_t spass_stream_p(hipStream_t st, const SPassArgs& a, int v) {
-  if (v == 1) return spass_stream_v<Real, N, 1, PLAIN>(st, a);
+  // a variant whose column tile does not divide the rows runs the default one
+  if (v == 1 && a.inner % SCfg<N, Real, 1>::TX == 0) return spass_stream_v<Real, N, 1, PLAIN>(st, a);
   if (v == 2) return spass_stream_v<Real, N, 2, PLAIN>(st, a);
   return spass_stream_v<Real, N, 0, PLAIN>(st, a);
 }

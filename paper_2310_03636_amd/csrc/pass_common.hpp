@@ -29,7 +29,8 @@ struct XCfg {
 
 // strided pass: radix R, TX adjacent columns per workgroup (TX x N/R threads).
 // Step-pass variants: V = 0 the default, V = 1 half the columns (radix 16 on 512
-// and radix 32 on 1024 for FP32), V = 2 radix 8.
+// and radix 32 on 1024 for FP32; twice the columns on FP32 columns of 256),
+// V = 2 radix 8.
 template <int N, typename Real, int V = 0>
 struct SCfg {
   static constexpr int R0 = N <= 8 ? N : (N <= 128 ? 8 : 16);
@@ -44,7 +45,11 @@ struct SCfg {
   static constexpr int CB = int(sizeof(Cx<Real>));
   static constexpr int TXRAW = 65536 / (N * CB);
   static constexpr int TX0 = TXRAW >= 16 ? 16 : (TXRAW >= 8 ? 8 : 4);
-  static constexpr int TX1 = (V == 1 && C1024) ? 16 : ((V == 1 && TX0 > 4 && !C512) ? TX0 / 2 : TX0);
+  // variant 1 of FP32 columns of 256: 32 columns (256-byte row segments, 64 KB
+  // of LDS, two workgroups per CU)
+  static constexpr bool W256 = V == 1 && N == 256 && sizeof(Real) == 4;
+  static constexpr int TX1 =
+      W256 ? 32 : ((V == 1 && C1024) ? 16 : ((V == 1 && TX0 > 4 && !C512) ? TX0 / 2 : TX0));
   // keep workgroups within 1024 threads
   static constexpr int TX = TX1 * T > 1024 ? 1024 / T : TX1;
   static constexpr int THREADS = TX * T;

@@ -716,8 +716,11 @@ def test_graph_option_validation(lib):
 
 
 # ------------------------------------------------------------------ step-pass variants and autotuning
-@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 128), (512, 512), (16, 512), (256, 1024), (1024, 64), (4096, 16)])
+@pytest.mark.parametrize("nx,ny", [(16, 8), (64, 128), (512, 512), (16, 512), (256, 1024), (1024, 64), (4096, 16),
+                                   (64, 256), (16, 256)])
 def test_every_step_variant_matches_oracle(lib, nx, ny):
+    # (64, 256): two 32-column tiles of variant 1 on 256-point columns;
+    # (16, 256): rows narrower than that tile, where variant 1 runs the default
     grid = (2, (nx, ny), 0.5, 2)
     og = O.Grid(2, (nx, ny), 0.5, 2)
     psi0 = random_field(nx + ny, og.shape, noise=0.4)
@@ -727,6 +730,25 @@ def test_every_step_variant_matches_oracle(lib, nx, ny):
             sim = lib.Sim([grid], P1, dtype=dtype)
             lib.set_variant(sim.ctx, 0, nx, v)
             lib.set_variant(sim.ctx, 1, ny, v)
+            sim.set_fields([psi0])
+            sim.step(1, 0.02)
+            assert rel(sim.fields()[0], ref) < tol, (dtype, v)
+            sim.close()
+
+
+@pytest.mark.parametrize("n", [(32, 256, 16), (16, 32, 256)])
+def test_every_strided_variant_3d(lib, n):
+    """Every strided-pass variant on a 256-point y or z axis of a 3D grid (one
+    32-column tile across 32 rows of x, and 16 tiles across the 16 x 32 plane)."""
+    grid = (3, n, 0.5, 2)
+    og = O.Grid(3, n, 0.5, 2)
+    psi0 = random_field(n[1] + 3 * n[2], og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(P3), og)
+    for dtype, tol in (("c128", 1e-13), ("c64", 2e-6)):
+        for v in range(lib.num_variants()):
+            sim = lib.Sim([grid], P3, dtype=dtype)
+            for a in (1, 2):
+                lib.set_variant(sim.ctx, 1, n[a], v)
             sim.set_fields([psi0])
             sim.step(1, 0.02)
             assert rel(sim.fields()[0], ref) < tol, (dtype, v)
