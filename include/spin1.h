@@ -308,7 +308,18 @@ SPIN1_API int spin1_set_variant(spin1_ctx* ctx, int32_t pass, int32_t n, int32_t
  *   and 2 = three thread groups per sample, one per component, regrouped
  *   through LDS for the local update (shorter step latency; Nx <= 2048, the
  *   pencil form otherwise); 1 = one thread group per sample holding all three
- *   components.  Same map either way. */
+ *   components.  Same map either way.
+ * SPIN1_OPT_STREAMING_STORES: how the streaming x and y/z passes of spin1_step
+ *   write the field back.  SPIN1_STORES_AUTO (default) = non-temporal stores
+ *   (the written lines are not kept in the caches) when the fields of all
+ *   bound groups together exceed 512 MiB (complex64) or 768 MiB (complex128),
+ *   ordinary stores otherwise;
+ *   SPIN1_STORES_CACHED and SPIN1_STORES_STREAMING force one form.  A field
+ *   that fits the last-level cache (256 MB on MI355X) is read back in part
+ *   from it by the next pass, which ordinary stores keep possible; beyond
+ *   about twice that size the cache holds little of the field and the
+ *   non-temporal stores leave it to the loads.  Same results, bit for bit,
+ *   either way. */
 enum spin1_option {
   SPIN1_OPT_GRAPHS = 0,
   SPIN1_OPT_GRAPH_MAX_STEPS = 1,
@@ -317,8 +328,10 @@ enum spin1_option {
   SPIN1_OPT_SCHEME = 4,
   SPIN1_OPT_FP32_TWIDDLES = 5,
   SPIN1_OPT_CONCURRENT_GROUPS = 6,
-  SPIN1_OPT_1D_KERNEL = 7
+  SPIN1_OPT_1D_KERNEL = 7,
+  SPIN1_OPT_STREAMING_STORES = 8
 };
+enum spin1_stores { SPIN1_STORES_AUTO = 0, SPIN1_STORES_CACHED = 1, SPIN1_STORES_STREAMING = 2 };
 enum spin1_scheme { SPIN1_SCHEME_STRANG = 0, SPIN1_SCHEME_PAPER = 1 };
 enum spin1_twiddles { SPIN1_TWIDDLES_COMPENSATED = 0, SPIN1_TWIDDLES_DITHERED = 1 };
 SPIN1_API int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value);

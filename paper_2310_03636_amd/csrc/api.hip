@@ -270,6 +270,7 @@ struct spin1_ctx {
   int kernel_1d = 0;  // 0 automatic, 1 one thread group per sample, 2 component groups
   int scheme = SPIN1_SCHEME_STRANG;
   bool dithered_tables = true;  // FP32 streaming passes: dithered float tables
+  int stores = SPIN1_STORES_AUTO;  // field stores of the streaming step passes
   // groups outside the grouped x-pass run on streams of their own (default
   // priority), forked from and joined back into the caller's stream per call
   bool concurrent = true;
@@ -436,8 +437,28 @@ int upload_shells(spin1_ctx* ctx, GroupState& G) {
   return SPIN1_OK;
 }
 
+// Non-temporal field stores in the streaming step passes: forced by the
+// option, else when the bound fields together exceed 512 MiB (complex64) or
+// 768 MiB (complex128).  Measured on 2D 512^2 batches (MI355X, 256 MB
+// last-level cache), split-step time with non-temporal against ordinary
+// stores: complex64 +3 to +4% up to 64 samples (403 MB: the next pass reads
+// part of the field from the cache), +1.2% at 80 (503 MB), level at 96
+// (604 MB), -3 to -5% from 128 (805 MB) to 384 samples (2.4 GB); complex128
+// +3% up to 48 samples (604 MB), level to +3% at 64 (805 MB), -1.4 to -2.2%
+// from 96 (1.2 GB) to 192 samples (2.4 GB).
+constexpr double kStreamingStoreBytesC64 = double(size_t(512) << 20);
+constexpr double kStreamingStoreBytesC128 = double(size_t(768) << 20);
+bool streaming_stores(const spin1_ctx* ctx) {
+  if (ctx->stores != SPIN1_STORES_AUTO) return ctx->stores == SPIN1_STORES_STREAMING;
+  double bytes = 0.0;
+  for (const GroupState& G : ctx->groups)
+    bytes += 3.0 * double(G.geo.S) * double(G.geo.sites) * (ctx->dbl ? 16.0 : 8.0);
+  return bytes > (ctx->dbl ? kStreamingStoreBytesC128 : kStreamingStoreBytesC64);
+}
+
 XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
   XPassArgs a{};
+  a.nt = streaming_stores(ctx) ? 1 : 0;
   a.psi = G.psi;
   a.pot = G.pot;
   a.tw = at(ctx, G.lay.tw[0]);
@@ -455,6 +476,7 @@ XPassArgs xargs(spin1_ctx* ctx, const GroupState& G) {
 
 SPassArgs sargs(spin1_ctx* ctx, const GroupState& G, int axis, void* field, int64_t nfield) {
   SPassArgs a{};
+  a.nt = streaming_stores(ctx) ? 1 : 0;
   a.psi = field;
   a.tw = at(ctx, G.lay.tw[axis]);
   a.ph = at(ctx, G.lay.ph[axis]);
@@ -1436,6 +1458,12 @@ int spin1_set_option(spin1_ctx* ctx, int32_t option, int64_t value) {
       if (value != SPIN1_TWIDDLES_COMPENSATED && value != SPIN1_TWIDDLES_DITHERED)
         return fail(SPIN1_EINVAL, "unknown twiddle precision");
       ctx->dithered_tables = value == SPIN1_TWIDDLES_DITHERED;
+      ctx->version++;
+      return SPIN1_OK;
+    case SPIN1_OPT_STREAMING_STORES:
+      if (value != SPIN1_STORES_AUTO && value != SPIN1_STORES_CACHED && value != SPIN1_STORES_STREAMING)
+        return fail(SPIN1_EINVAL, "unknown store form");
+      ctx->stores = int(value);
       ctx->version++;
       return SPIN1_OK;
     case SPIN1_OPT_GROUPED_X:

@@ -20,6 +20,20 @@ struct alignas(2 * sizeof(Real)) Cx {
   Real re, im;
 };
 
+// Store of one complex value; NT: non-temporal (the line is not kept in the
+// caches: for fields that the next pass cannot find in the last-level cache
+// anyway)
+template <bool NT, typename Real>
+__device__ __forceinline__ void put(Cx<Real>* p, Cx<Real> c) {
+  if constexpr (NT) {
+    typedef Real V __attribute__((ext_vector_type(2)));
+    const V v = {c.re, c.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+  } else {
+    *p = c;
+  }
+}
+
 template <typename Real>
 __device__ __forceinline__ Cx<Real> operator+(Cx<Real> a, Cx<Real> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename Real>

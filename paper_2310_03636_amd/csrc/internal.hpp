@@ -81,6 +81,7 @@ struct XPassArgs {
   double power_scale;  // SF_POWER: 1 / N_sites
   int lg_rows;      // log2(rows), set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
+  int nt;           // STEP (streaming kernel): non-temporal stores of the field
   int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
 };
 
@@ -122,6 +123,7 @@ struct SPassArgs {
   double power_scale;
   int lg_tiles, lg_outer;  // log2 of (inner / TX) and of outer, set by the launcher
   int reverse;      // STEP (streaming kernel): walk the work items from the last one
+  int nt;           // STEP (streaming kernel): non-temporal stores of the field
   int64_t tick;     // STEP: index of the step in the call (dithered single-precision tables)
 };
 

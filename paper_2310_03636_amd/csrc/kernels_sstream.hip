@@ -21,7 +21,9 @@ namespace spin1 {
 // load issued after the prefetch could only be consumed once the whole
 // prefetch had arrived (the vector-memory counter retires in order).
 // PLAIN: plain complex twiddles and phase factors, dithered per step (FP32).
-template <typename Real, int N, int V, bool PLAIN>
+// NT: non-temporal stores of the field (a template parameter: a branch on the
+// store form inside the kernel costs the wide tiles up to 90 registers).
+template <typename Real, int N, int V, bool PLAIN, bool NT>
 __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SPassArgs a, int64_t items) {
   using C = Cx<Real>;
   constexpr int R = SCfg<N, Real, V>::R, T = SCfg<N, Real, V>::T, TX = SCfg<N, Real, V>::TX;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
     fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), static_cast<const PE*>(ph),
                                    static_cast<const PE*>(nullptr));
 #pragma unroll
-    for (int e = 0; e < R; ++e) *reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)) = v[e];
+    for (int e = 0; e < R; ++e) put<NT>(reinterpret_cast<C*>(dst + (lane_off + uint32_t(e) * step_e)), v[e]);
   }
 }
 
@@ -102,9 +104,15 @@ static hipError_t spass_stream_v(hipStream_t st, const SPassArgs& a) {
   SPassArgs b = a;
   b.lg_tiles = ilog2(a.inner / TX);
   b.lg_outer = ilog2(a.outer);
-  const int64_t grid = stream_grid(k_spass_stream<Real, N, V, PLAIN>, SCfg<N, Real, V>::THREADS, blocks);
-  (void)launch_kernel((k_spass_stream<Real, N, V, PLAIN>), dim3(unsigned(grid)), dim3(SCfg<N, Real, V>::THREADS), 0,
-                     st, b, blocks);
+  if (a.nt) {
+    const int64_t grid = stream_grid(k_spass_stream<Real, N, V, PLAIN, true>, SCfg<N, Real, V>::THREADS, blocks);
+    (void)launch_kernel((k_spass_stream<Real, N, V, PLAIN, true>), dim3(unsigned(grid)),
+                        dim3(SCfg<N, Real, V>::THREADS), 0, st, b, blocks);
+  } else {
+    const int64_t grid = stream_grid(k_spass_stream<Real, N, V, PLAIN, false>, SCfg<N, Real, V>::THREADS, blocks);
+    (void)launch_kernel((k_spass_stream<Real, N, V, PLAIN, false>), dim3(unsigned(grid)),
+                        dim3(SCfg<N, Real, V>::THREADS), 0, st, b, blocks);
+  }
   return hipGetLastError();
 }
 

@@ -115,11 +115,20 @@ __global__ __launch_bounds__((XCfg<N, Real, V>::THREADS)) __attribute__((
     if (a.tau_post != 0.0) local_update_sites<Real, R, T, POT ? POT_ALWAYS : POT_NEVER>(v, t, Real(a.tau_post), c0, c1, prow,
                                                                            a.tau_post);
     if (active) {
+      if (a.nt) {
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        C* dst = psi + comp_off(pid, m);
+        for (int m = 0; m < 3; ++m) {
+          C* dst = psi + comp_off(pid, m);
 #pragma unroll
-        for (int e = 0; e < R; ++e) dst[uint32_t(t + e * T)] = v[m][e];
+          for (int e = 0; e < R; ++e) put<true>(&dst[uint32_t(t + e * T)], v[m][e]);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          C* dst = psi + comp_off(pid, m);
+#pragma unroll
+          for (int e = 0; e < R; ++e) put<false>(&dst[uint32_t(t + e * T)], v[m][e]);
+        }
       }
     }
   }

@@ -36,6 +36,8 @@ SCHEME_STRANG, SCHEME_PAPER = 0, 1
 OPT_FP32_TWIDDLES = 5
 OPT_CONCURRENT_GROUPS = 6
 OPT_1D_KERNEL = 7
+OPT_STREAMING_STORES = 8
+STORES_AUTO, STORES_CACHED, STORES_STREAMING = 0, 1, 2
 TWIDDLES_COMPENSATED, TWIDDLES_DITHERED = 0, 1
 
 KERNEL_KINDS = ["xpass", "ypass", "zpass", "local", "spectrum", "shells", "observables", "other"]

@@ -713,6 +713,35 @@ def test_graph_option_validation(lib):
         sim.set_option(lib.OPT_GRAPH_MAX_STEPS, 0)
     with pytest.raises(lib.Spin1Error):
         sim.set_option(99, 1)
+    with pytest.raises(lib.Spin1Error):
+        sim.set_option(lib.OPT_STREAMING_STORES, 3)
+
+
+@pytest.mark.parametrize("grid,p", [((2, (64, 256), 0.5, 3), P1), ((3, (32, 16, 256), 0.5, 2), P3)])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_streaming_stores_give_the_same_fields(lib, grid, p, dtype):
+    """The non-temporal and the ordinary field stores of the step passes give
+    the same fields bit for bit (every variant of the strided pass, graphs on),
+    and both match the oracle step."""
+    og = O.Grid(grid[0], grid[1], grid[2], grid[3])
+    psi0 = random_field(41, og.shape, noise=0.4)
+    ref = O.strang_step(psi0, 0.02, oparams(p), og)
+    for v in range(lib.num_variants()):
+        out = []
+        for form in (lib.STORES_CACHED, lib.STORES_STREAMING, lib.STORES_AUTO):
+            sim = lib.Sim([grid], p, dtype=dtype)
+            sim.set_option(lib.OPT_STREAMING_STORES, form)
+            for a in range(1, grid[0]):
+                lib.set_variant(sim.ctx, 1, grid[1][a], v)
+            sim.set_fields([psi0])
+            sim.step(1, 0.02)
+            out.append(sim.fields()[0])
+            sim.step(5, 0.02)
+            out.append(sim.fields()[0])
+            sim.close()
+        assert np.array_equal(out[0], out[2]) and np.array_equal(out[1], out[3]), (dtype, v)
+        assert np.array_equal(out[0], out[4]) and np.array_equal(out[1], out[5]), (dtype, v)
+        assert rel(out[2], ref) < (1e-13 if dtype == "c128" else 2e-6), (dtype, v)
 
 
 # ------------------------------------------------------------------ step-pass variants and autotuning
