@@ -83,8 +83,10 @@ __global__ __launch_bounds__((SCfg<N, Real, V>::THREADS)) void k_spass_stream(SP
     const int64_t next = item + gridDim.x;
     if (next < items) {
       const char* src = tile_base(next);
+      if constexpr (SCfg<N, Real, V>::PRIO) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
       for (int e = 0; e < R; ++e) nxt[e] = *reinterpret_cast<const C*>(src + (lane_off + uint32_t(e) * step_e));
+      if constexpr (SCfg<N, Real, V>::PRIO) __builtin_amdgcn_s_setprio(0);
     }
     fft_halfphase_ifft<Real, N, R>(v, t, L, static_cast<const TE*>(tw), static_cast<const PE*>(ph),
                                    static_cast<const PE*>(nullptr));
