@@ -244,8 +244,9 @@ SPIN1_API int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every,
  * spin1_autotune copies each bound field into scratch_dev (at least the
  * largest field; the bound fields are not touched), times every variant of
  * every pass the bound groups use (reps launches each, HIP events on the
- * context's stream; synchronises) and keeps the fastest per (pass, n, dtype)
- * for this context.  spin1_get_variant / spin1_set_variant read and restore
+ * context's stream; synchronises) in three sweeps after a warm-up sweep, the
+ * variants taking turns, and keeps the variant with the fastest sweep per
+ * (pass, n, dtype) for this context.  spin1_get_variant / spin1_set_variant read and restore
  * the choices (e.g. from a cache file). */
 SPIN1_API int32_t spin1_num_variants(void);
 SPIN1_API int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t reps);

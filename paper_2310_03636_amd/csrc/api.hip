@@ -1355,7 +1355,11 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
     (void)hipEventDestroy(ev[0]);
     return fail(SPIN1_EHIP, "hipEventCreate");
   }
-  double total[2][13][8] = {};
+  // fastest timed sweep per (pass, log2 n, variant)
+  double best_ms[2][13][8];
+  for (auto& a : best_ms)
+    for (auto& b : a)
+      for (double& c : b) c = 1e300;
   bool seen[2][13] = {};
   const int nv = step_variants();
   rc = SPIN1_OK;
@@ -1374,8 +1378,10 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
       const int pass = axis == 0 ? 0 : 1;
       const int lg = log2_of(G.geo.n[axis]);
       seen[pass][lg] = true;
-      // sweep 0 brings the clocks up and is not counted; sweep 1 is timed
-      for (int sweep = 0; sweep < 2 && !rc; ++sweep)
+      // sweep 0 brings the clocks up and is not counted; sweeps 1..3 are
+      // timed, the variants taking turns, and each variant keeps its fastest
+      // (one sweep disturbed by anything else on the GPU changes no choice)
+      for (int sweep = 0; sweep < 4 && !rc; ++sweep)
       for (int v = 0; v < nv && !rc; ++v) {
         auto launch = [&]() {
           if (pass == 0) {
@@ -1398,7 +1404,7 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
           rc = hip_fail(e, "autotune timing");
           break;
         }
-        if (sweep == 1) total[pass][lg][v] += double(ms);
+        if (sweep > 0 && double(ms) < best_ms[pass][lg][v]) best_ms[pass][lg][v] = double(ms);
       }
     }
     if (rc) break;
@@ -1411,7 +1417,7 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
       if (!seen[pass][lg]) continue;
       int best = 0;
       for (int v = 1; v < nv; ++v)
-        if (total[pass][lg][v] < total[pass][lg][best]) best = v;
+        if (best_ms[pass][lg][v] < best_ms[pass][lg][best]) best = v;
       ctx->variant[pass][ctx->dbl ? 1 : 0][lg] = int8_t(best);
     }
   ctx->version++;
