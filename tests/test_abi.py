@@ -33,6 +33,21 @@ def test_library_exports_every_declared_symbol(abi):
     assert exported == set(header_functions())
 
 
+def test_binding_constants_match_the_header(abi):
+    """Every enum value of the header (status codes, dtypes, options and their
+    values, kernel kinds) has the same value in the binding."""
+    consts = re.findall(r"\bSPIN1_([A-Z0-9_]+) = (-?\d+)", open(HEADER).read())
+    assert len(consts) >= 30
+    for name, value in consts:
+        if name.startswith("K_"):
+            if name == "K_COUNT":
+                assert len(abi.KERNEL_KINDS) == int(value)
+            else:
+                assert abi.KERNEL_KINDS[int(value)] == name[2:].lower(), name
+        else:
+            assert getattr(abi, name) == int(value), name
+
+
 def test_header_compiles_as_c99(tmp_path):
     src = tmp_path / "h.c"
     src.write_text('#include "spin1.h"\nint main(void){ spin1_grid g = {1, {8, 1, 1}, 0.5, 1}; (void)g; return 0; }\n')
