@@ -84,6 +84,23 @@ def test_3d_256_8_samples_full_size_invariants(lib):
     assert err < 1e-4, err
 
 
+def test_2d_512_384_samples_full_size(lib):
+    """The 2.4 GB batch of 384 samples of 512^2 (beyond the last-level cache:
+    non-temporal field stores) in the benchmark's launch configuration, two
+    split steps; its first and last samples against the oracle run on them."""
+    g = (2, (512, 512), 0.5, 384)
+    sim = lib.Sim([g], P2, dtype="c64")
+    sim.init_wigner(1002)
+    sim.autotune(reps=1)
+    sim.step(2, 0.02)
+    f = sim.field_tensor(0)
+    got = [f[s].cpu().numpy().astype(np.complex128) for s in (0, 383)]
+    sim.close()
+    ref = oracle_samples(1002, g, P2, 0, [0, 383], 2, 0.02)
+    for k in range(2):
+        assert rel(got[k], ref[k]) < 1e-5, k
+
+
 @pytest.mark.timeout(600)
 def test_3d_256_8_samples_full_size_last_sample_against_oracle(lib):
     """One split step of the full 256^3 x 8 batch in the benchmark's launch
