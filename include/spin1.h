@@ -246,7 +246,10 @@ SPIN1_API int spin1_adjoint(spin1_ctx* ctx, int64_t n, double dt, int64_t every,
  * every pass the bound groups use (reps launches each, HIP events on the
  * context's stream; synchronises) in three sweeps after a warm-up sweep, the
  * variants taking turns, and keeps the variant with the fastest sweep per
- * (pass, n, dtype) for this context.  spin1_get_variant / spin1_set_variant read and restore
+ * (pass, n, dtype) for this context.  It then retries each choice used by a
+ * 2D or 3D group, one (pass, n) at a time, by timing whole split steps of the
+ * groups that use it on the scratch copy, and keeps the variant with the
+ * least step time.  spin1_get_variant / spin1_set_variant read and restore
  * the choices (e.g. from a cache file). */
 SPIN1_API int32_t spin1_num_variants(void);
 SPIN1_API int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int32_t reps);

@@ -1409,17 +1409,73 @@ int spin1_autotune(spin1_ctx* ctx, void* scratch_dev, size_t scratch_bytes, int3
     }
     if (rc) break;
   }
+  if (!rc)
+    for (int pass = 0; pass < 2; ++pass)
+      for (int lg = 0; lg < 13; ++lg) {
+        if (!seen[pass][lg]) continue;
+        int best = 0;
+        for (int v = 1; v < nv; ++v)
+          if (best_ms[pass][lg][v] < best_ms[pass][lg][best]) best = v;
+        ctx->variant[pass][ctx->dbl ? 1 : 0][lg] = int8_t(best);
+      }
+  // Refinement in context: a pass variant interacts with the passes around
+  // it (what the last-level cache holds when it starts, the direction the
+  // previous pass walked), so each choice of a 2D/3D group is retried, one
+  // (pass, n) at a time, by timing whole split steps of the groups that use
+  // it, each on its scratch copy; the variant with the least total time stays.
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  for (int pass = 0; pass < 2 && !rc; ++pass)
+    for (int lg = 0; lg < 13 && !rc; ++lg) {
+      if (!seen[pass][lg]) continue;
+      const int n = 1 << lg;
+      std::vector<const GroupState*> users;
+      for (const GroupState& G : ctx->groups) {
+        if (G.geo.dim < 2) continue;
+        bool uses = pass == 0 && G.geo.n[0] == n;
+        for (int a = 1; a < G.geo.dim && pass == 1; ++a) uses = uses || G.geo.n[a] == n;
+        if (uses) users.push_back(&G);
+      }
+      if (users.empty()) continue;
+      int8_t& slot = ctx->variant[pass][ctx->dbl ? 1 : 0][lg];
+      int best = slot;
+      double best_total = 1e300;
+      for (int v = 0; v < nv && !rc; ++v) {
+        slot = int8_t(v);
+        double total = 0.0;
+        for (const GroupState* G : users) {
+          const size_t fb = size_t(G->geo.S) * 3 * size_t(G->geo.sites) * (ctx->dbl ? 16 : 8);
+          hipError_t e = hipMemcpyAsync(scratch_dev, G->psi, fb, hipMemcpyDeviceToDevice, ctx->stream);
+          if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune copy");
+            break;
+          }
+          // one step to warm up, three timed
+          rc = enqueue_group_step(ctx, *G, scratch_dev, dt, 0.0, nullptr, 0);
+          if (!rc && (e = hipEventRecord(ev[0], ctx->stream)) != hipSuccess) rc = hip_fail(e, "autotune timing");
+          for (int i = 1; i <= 3 && !rc; ++i) rc = enqueue_group_step(ctx, *G, scratch_dev, dt, 0.0, nullptr, i);
+          if (rc) break;
+          float ms = 0.0f;
+          e = hipEventRecord(ev[1], ctx->stream);
+          if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+          if (e != hipSuccess) {
+            rc = hip_fail(e, "autotune timing");
+            break;
+          }
+          total += double(ms);
+        }
+        if (!rc && total < best_total) {
+          best_total = total;
+          best = v;
+        }
+      }
+      slot = int8_t(best);
+    }
+  ctx->prof = prof;
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   if (rc) return rc;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int lg = 0; lg < 13; ++lg) {
-      if (!seen[pass][lg]) continue;
-      int best = 0;
-      for (int v = 1; v < nv; ++v)
-        if (best_ms[pass][lg][v] < best_ms[pass][lg][best]) best = v;
-      ctx->variant[pass][ctx->dbl ? 1 : 0][lg] = int8_t(best);
-    }
   ctx->version++;
   return SPIN1_OK;
 }
